@@ -1,0 +1,154 @@
+"""Plain serial FP64 CPU oracle for the reaction-diffusion array program.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this package; the GPU library never
+does, and this package imports nothing from it.  The arithmetic lives in
+``rd3d_oracle.c`` (built with gcc, no FMA contraction); this module only
+marshals NumPy arrays into it.  Where each function comes from in the paper
+is stated in the C source.
+
+Arrays are float64, C-contiguous, shape ``(nz, ny, nx)`` (x fastest).
+Boundary modes: 0 = ghost-zero Dirichlet, 1 = periodic.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rd3d_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+DIRICHLET0 = 0
+PERIODIC = 1
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (serial, -O3, no FP contraction)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call([
+            "gcc", "-std=c11", "-O3", "-ffp-contract=off", "-fno-fast-math",
+            "-fPIC", "-shared", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm",
+        ])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        i64 = ctypes.c_int64
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        d = ctypes.c_double
+        lib.oracle_run.argtypes = [i64, i64, i64, dp, dp, d, d, d, d, d,
+                                   ctypes.c_int, ctypes.c_int, dp, dp, dp]
+        lib.oracle_run.restype = ctypes.c_int
+        lib.oracle_run_box.argtypes = [i64, i64, i64, dp, dp, d, d, d, d, d,
+                                       ctypes.c_int, ctypes.c_int, i64p, i64p, dp]
+        lib.oracle_run_box.restype = ctypes.c_int
+        lib.oracle_adjoint.argtypes = [i64, i64, i64, dp, dp, dp, d, d, d, d, d,
+                                       ctypes.c_int, ctypes.c_int, dp, dp]
+        lib.oracle_adjoint.restype = ctypes.c_int
+        lib.oracle_half_sq_dist.argtypes = [i64, dp, dp]
+        lib.oracle_half_sq_dist.restype = d
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray | None):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _field(a) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.ndim != 3:
+        raise ValueError("fields are 3-D arrays shaped (nz, ny, nx)")
+    return a
+
+
+def _coeffs(c):
+    return (float(c["alpha"]), float(c["beta"]), float(c["gamma"]),
+            float(c["h"]), float(c["dt"]))
+
+
+def run(u0, f, coeffs: dict, T: int, bc: int, norms: bool = True):
+    """T steps on the whole grid.
+
+    Returns ``(u_T, energy[T], resid[T])`` where energy[t-1] = sum u_t^2 and
+    resid[t-1] = ||u_t - u_{t-1}||_2 for t = 1..T.
+    """
+    u0 = _field(u0)
+    f = _field(f)
+    if f.shape != u0.shape:
+        raise ValueError("u0 and f must have the same shape")
+    nz, ny, nx = u0.shape
+    uT = np.empty_like(u0)
+    e = np.empty(max(T, 0), dtype=np.float64)
+    r = np.empty(max(T, 0), dtype=np.float64)
+    rc = _load().oracle_run(nx, ny, nz, _ptr(u0), _ptr(f), *_coeffs(coeffs),
+                            int(bc), int(T), _ptr(uT),
+                            _ptr(e) if norms else None, _ptr(r) if norms else None)
+    if rc != 0:
+        raise ValueError(f"oracle_run failed with code {rc}")
+    return uT, e, r
+
+
+def run_box(u0, f, coeffs: dict, T: int, bc: int, lo, hi) -> np.ndarray:
+    """u_T on the box [lo, hi) given as (x, y, z) triples; returns (hz, hy, hx)."""
+    u0 = _field(u0)
+    f = _field(f)
+    nz, ny, nx = u0.shape
+    blo = (ctypes.c_int64 * 3)(*[int(v) for v in lo])
+    bhi = (ctypes.c_int64 * 3)(*[int(v) for v in hi])
+    shape = (int(hi[2]) - int(lo[2]), int(hi[1]) - int(lo[1]), int(hi[0]) - int(lo[0]))
+    out = np.empty(shape, dtype=np.float64)
+    rc = _load().oracle_run_box(nx, ny, nz, _ptr(u0), _ptr(f), *_coeffs(coeffs),
+                                int(bc), int(T), blo, bhi, _ptr(out))
+    if rc != 0:
+        raise ValueError(f"oracle_run_box failed with code {rc}")
+    return out
+
+
+def adjoint(u0, f, lam_T, coeffs: dict, T: int, bc: int):
+    """Gradient through T steps given the seed lam_T = dL/du_T.
+
+    Returns ``(dL/du0, dL/dalpha, dL/dbeta)``.
+    """
+    u0 = _field(u0)
+    f = _field(f)
+    lam_T = _field(lam_T)
+    nz, ny, nx = u0.shape
+    g = np.empty_like(u0)
+    gab = np.empty(2, dtype=np.float64)
+    rc = _load().oracle_adjoint(nx, ny, nz, _ptr(u0), _ptr(f), _ptr(lam_T),
+                                *_coeffs(coeffs), int(bc), int(T), _ptr(g), _ptr(gab))
+    if rc != 0:
+        raise ValueError(f"oracle_adjoint failed with code {rc}")
+    return g, float(gab[0]), float(gab[1])
+
+
+def half_sq_dist(a, b) -> float:
+    """0.5 * sum (a - b)^2 with a compensated sum (the config loss)."""
+    a = np.ascontiguousarray(a, dtype=np.float64).ravel()
+    b = np.ascontiguousarray(b, dtype=np.float64).ravel()
+    return float(_load().oracle_half_sq_dist(a.size, _ptr(a), _ptr(b)))
+
+
+def grad_of_half_sq_dist(u0, f, u_tgt, coeffs: dict, T: int, bc: int):
+    """Loss L = 0.5*||u_T - u_tgt||^2 and its gradient (dL/du0, dL/dalpha, dL/dbeta)."""
+    uT, _, _ = run(u0, f, coeffs, T, bc, norms=False)
+    loss = half_sq_dist(uT, u_tgt)
+    lam_T = uT - _field(u_tgt)
+    g, ga, gb = adjoint(u0, f, lam_T, coeffs, T, bc)
+    return loss, g, ga, gb

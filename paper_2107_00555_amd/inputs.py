@@ -1,0 +1,137 @@
+"""Seeded synthetic inputs for the reaction-diffusion workloads.
+
+This module holds the random input generators only: none of the program's
+arithmetic.  Both the GPU path's tests/benchmark and the CPU oracle consume
+the arrays it returns, so the two sides never have to agree on anything but
+these arrays.
+
+Every stream draws from ``np.random.default_rng(SeedSequence([seed, s]))``
+with a fixed stream id ``s``:
+
+    0  u0             initial state
+    1  f              source field
+    2  u_tgt          loss target
+    3  FD directions  finite-difference probes
+
+Arrays are float64, C order, shape ``(nz, ny, nx)`` (x is the fastest axis).
+Float32 workloads cast these once (round to nearest even).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+STREAM_U0 = 0
+STREAM_F = 1
+STREAM_TGT = 2
+STREAM_FD = 3
+
+
+def rng(seed: int, stream: int) -> np.random.Generator:
+    return np.random.default_rng(np.random.SeedSequence([int(seed), int(stream)]))
+
+
+def uniform(nx: int, ny: int, nz: int, seed: int, stream: int) -> np.ndarray:
+    """i.i.d. uniform[-1, 1] field of shape (nz, ny, nx)."""
+    return rng(seed, stream).uniform(-1.0, 1.0, size=(nz, ny, nx))
+
+
+def sinusoid_params(seed: int, stream: int = STREAM_F, count: int = 8):
+    """Draw ``count`` low-frequency modes: integer wave numbers m in
+    {-4..4}^3 (redrawn if all zero), amplitude a ~ U[-1,1], phase phi ~ U[0,2pi)."""
+    r = rng(seed, stream)
+    modes = []
+    for _ in range(count):
+        m = r.integers(-4, 5, size=3)
+        while not m.any():
+            m = r.integers(-4, 5, size=3)
+        a = r.uniform(-1.0, 1.0)
+        phi = r.uniform(0.0, 2.0 * np.pi)
+        modes.append((int(m[0]), int(m[1]), int(m[2]), float(a), float(phi)))
+    return modes
+
+
+def sinusoids(nx: int, ny: int, nz: int, seed: int, stream: int = STREAM_F,
+              count: int = 8, out: np.ndarray | None = None,
+              zchunk: int = 32) -> np.ndarray:
+    """f = sum_j a_j sin(2 pi (mx x/nx + my y/ny + mz z/nz) + phi_j).
+
+    Periodic on the grid and smooth.  Evaluated as
+    sin(A + B) = sin A cos B + cos A sin B with A over (y, x) and B over z,
+    in z-chunks, so the 512^3 and 1024x1024x512 grids stay cheap to build.
+    """
+    modes = sinusoid_params(seed, stream, count)
+    if out is None:
+        out = np.zeros((nz, ny, nx), dtype=np.float64)
+    else:
+        out[...] = 0.0
+    x = np.arange(nx, dtype=np.float64)
+    y = np.arange(ny, dtype=np.float64)
+    z = np.arange(nz, dtype=np.float64)
+    for mx, my, mz, a, phi in modes:
+        A = (2.0 * np.pi * (my * y / ny))[:, None] + (2.0 * np.pi * (mx * x / nx))[None, :] + phi
+        sA = a * np.sin(A)
+        cA = a * np.cos(A)
+        B = 2.0 * np.pi * (mz * z / nz)
+        sB = np.sin(B)
+        cB = np.cos(B)
+        for z0 in range(0, nz, zchunk):
+            z1 = min(nz, z0 + zchunk)
+            blk = out[z0:z1]
+            blk += sA[None, :, :] * cB[z0:z1, None, None]
+            blk += cA[None, :, :] * sB[z0:z1, None, None]
+    return out
+
+
+def fd_directions(nx: int, ny: int, nz: int, seed: int, count: int):
+    """Yield ``count`` probe directions (d_u ~ U[-1,1]^N, d_alpha ~ N(0,1),
+    d_beta ~ N(0,1)), drawn in order from the FD stream."""
+    r = rng(seed, STREAM_FD)
+    for _ in range(count):
+        du = r.uniform(-1.0, 1.0, size=(nz, ny, nx))
+        da = float(r.standard_normal())
+        db = float(r.standard_normal())
+        yield du, da, db
+
+
+# Named workloads: the grids, boundaries and coefficient sets the library is
+# measured and checked on.
+DIRICHLET0 = 0
+PERIODIC = 1
+
+BASE_COEFFS = dict(alpha=1.0, beta=0.1, gamma=0.5, h=1.0, dt=0.1)
+
+WORKLOADS = {
+    # 64^3 float64, ghost-zero boundary, u0 and f uniform, T=10, forward.
+    "plain_64": dict(shape=(64, 64, 64), dtype="f64", bc=DIRICHLET0, T=10,
+                     u0="uniform", f="uniform"),
+    # 512^3 float64, periodic, u0 uniform, f = 8 sinusoids, T=100.
+    "fwd_512_f64": dict(shape=(512, 512, 512), dtype="f64", bc=PERIODIC, T=100,
+                        u0="uniform", f="sinusoids"),
+    # Same generator, float32 storage and compute, FP64 norms.
+    "fwd_512_f32": dict(shape=(512, 512, 512), dtype="f32", bc=PERIODIC, T=100,
+                        u0="uniform", f="sinusoids"),
+    # 256^3 float64, ghost-zero, T=50, checkpoint every 10, loss 0.5||u_T-u_tgt||^2.
+    "grad_256_f64": dict(shape=(256, 256, 256), dtype="f64", bc=DIRICHLET0, T=50,
+                         ckpt_every=10, u0="uniform", f="uniform"),
+    # 1024x1024x512 float32, periodic, T=200, checkpoint every 20.
+    "grad_large_f32": dict(shape=(1024, 1024, 512), dtype="f32", bc=PERIODIC, T=200,
+                           ckpt_every=20, u0="uniform", f="sinusoids"),
+}
+
+
+def make_fields(workload: str | dict, seed: int = 0, shape=None):
+    """(u0, f) for a workload, float64, shape (nz, ny, nx); ``shape`` = (nx, ny, nz)
+    overrides the workload's grid."""
+    w = WORKLOADS[workload] if isinstance(workload, str) else workload
+    nx, ny, nz = shape if shape is not None else w["shape"]
+    u0 = uniform(nx, ny, nz, seed, STREAM_U0)
+    if w["f"] == "uniform":
+        f = uniform(nx, ny, nz, seed, STREAM_F)
+    else:
+        f = sinusoids(nx, ny, nz, seed, STREAM_F)
+    return u0, f
+
+
+def target(nx: int, ny: int, nz: int, seed: int = 0) -> np.ndarray:
+    """u_tgt ~ U[-1,1] for the gradient workloads."""
+    return uniform(nx, ny, nz, seed, STREAM_TGT)
