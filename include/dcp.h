@@ -1,0 +1,205 @@
+/*
+ * dcp.h -- C ABI of libdcp, the MI355X (gfx950) library for the fused
+ * reaction-diffusion array program
+ *
+ *     u' = u + dt * (alpha * Lap7(u) - beta * u^3 + gamma * f)
+ *     Lap7(u)[p] = (sum of the six face neighbours of p - 6 u[p]) / h^2
+ *
+ * applied T times on an (nx, ny, nz) grid, and for its adjoint.
+ *
+ * The program is one element-wise expression over a 7-point stencil, the
+ * class of NumPy array programs whose translation is described in Sec. 2.3
+ * of the paper (each operator becomes a map over the array; an expression is
+ * split into single-operator statements with one temporary each) and whose
+ * main GPU speed-up comes from the optimisations of Sec. 3.1 (greedy
+ * subgraph fusion of maps that share an iteration space, transient
+ * elimination, tiled write-conflict reductions).  The fused entry points
+ * compute the whole expression in one pass over the grid with no
+ * temporaries in memory; the unfused entry point runs the single-operator
+ * statements one kernel each, as the unoptimised program would.
+ *
+ * ---------------------------------------------------------------------------
+ * Conventions shared by every entry point
+ *
+ * Layout.  Fields are dense arrays of nx*ny*nz elements with x fastest:
+ *   element (x, y, z) is at index x + nx*(y + ny*z).
+ *   (A C-order array of shape (nz, ny, nx).)
+ *
+ * Element type.  dtype DCP_F64 (double) or DCP_F32 (float).  Every field
+ *   argument of one call has that type.  In DCP_F32 the coefficients are
+ *   rounded to float once per call and the arithmetic is float; the
+ *   diagnostic norms and the gradient reductions are accumulated in double.
+ *
+ * Boundary.  DCP_DIRICHLET0: a neighbour outside [0, n) along an axis reads
+ *   as 0 and every point of the grid is updated.  DCP_PERIODIC: the
+ *   neighbour index is taken modulo n (n = 1 and n = 2 included).
+ *
+ * Memory.  Every field, norm and gradient pointer is a DEVICE pointer owned
+ *   by the caller.  `coeffs` is a HOST pointer read during the call only.
+ *   The library never allocates or frees device memory: scratch space comes
+ *   from the caller's workspace `ws` of `ws_bytes` bytes (size it with
+ *   dcp_workspace_bytes; ws may be NULL when that size is 0).  The library
+ *   holds no global state; calls on different streams with disjoint
+ *   buffers may run concurrently.
+ *
+ * Execution.  Work is enqueued on `stream` (a hipStream_t; NULL is the
+ *   default stream) and the call returns without synchronising.  Results,
+ *   including the double-precision norm and gradient outputs, are valid once
+ *   the stream has reached the call.
+ *
+ * Errors.  Every entry point returns a dcp_status.  Argument errors
+ *   (DCP_E_NULL .. DCP_E_ALIAS) are detected before anything is enqueued:
+ *   no partial work is done and no output is touched.  DCP_E_HIP means a
+ *   HIP launch or copy failed; work enqueued before the failure may have
+ *   run.  Non-finite coefficients are rejected; unstable but finite ones are
+ *   not (the program is the caller's).
+ *
+ * Empty grids (nx, ny or nz equal to 0) are valid: fields are untouched and
+ * every requested norm or gradient sum is written as 0.
+ */
+#ifndef DCP_H
+#define DCP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DCP_OK = 0,
+    DCP_E_NULL = -1,      /* a required pointer is NULL                        */
+    DCP_E_SHAPE = -2,     /* negative extent, or nx*ny*nz*sizeof overflows     */
+    DCP_E_DTYPE = -3,     /* dtype is not DCP_F64 or DCP_F32                   */
+    DCP_E_BC = -4,        /* boundary is not DCP_DIRICHLET0 or DCP_PERIODIC    */
+    DCP_E_ARG = -5,       /* T < 0, ckpt_every < 1 with checkpoints, tblock
+                             out of range, h <= 0, non-finite coefficient,
+                             unknown impl or op                               */
+    DCP_E_WORKSPACE = -6, /* ws_bytes smaller than dcp_workspace_bytes(...)    */
+    DCP_E_ALIAS = -7,     /* an output overlaps an input it must not overlap   */
+    DCP_E_HIP = -100      /* a HIP launch or copy failed                       */
+} dcp_status;
+
+typedef enum { DCP_F64 = 0, DCP_F32 = 1 } dcp_dtype;
+typedef enum { DCP_DIRICHLET0 = 0, DCP_PERIODIC = 1 } dcp_bc;
+typedef enum { DCP_FUSED = 0, DCP_UNFUSED = 1 } dcp_impl;
+
+/* Operation selector for dcp_workspace_bytes. */
+typedef enum {
+    DCP_OP_STEP_FUSED = 0,
+    DCP_OP_STEP_UNFUSED = 1,
+    DCP_OP_RUN = 2,
+    DCP_OP_ADJOINT = 3
+} dcp_op;
+
+/* Scalars of the program.  h is the grid spacing on every axis (> 0). */
+typedef struct {
+    double alpha, beta, gamma, h, dt;
+} dcp_coeffs;
+
+/*
+ * Workspace size in bytes for one call of `op` with these arguments.
+ *   impl        DCP_FUSED or DCP_UNFUSED (DCP_OP_RUN only; ignored otherwise)
+ *   T           number of steps (DCP_OP_RUN, DCP_OP_ADJOINT)
+ *   ckpt_every  checkpoint interval k (DCP_OP_ADJOINT: >= 1; ignored otherwise)
+ *   tblock      steps per pass over memory (DCP_OP_RUN, fused only; 1 = none)
+ *   norms       nonzero if the call will request norms (energy/resid/norms2)
+ * The size is an upper bound valid for any pointer alignment.  Writes it to
+ * *bytes (a host pointer).  Returns DCP_OK or an argument error.
+ */
+int dcp_workspace_bytes(int op, int dtype, int impl, int64_t nx, int64_t ny,
+                        int64_t nz, int32_t T, int32_t ckpt_every,
+                        int32_t tblock, int norms, size_t *bytes);
+
+/*
+ * One fused step: u_out = u + dt*(alpha*Lap7(u) - beta*u^3 + gamma*f),
+ * computed in one pass (greedy subgraph fusion and transient elimination of
+ * Sec. 3.1): reads u and f once, writes u_out once, no temporaries.
+ *   u, f     [N]  in   (may alias each other)
+ *   u_out    [N]  out  (must not overlap u or f)
+ *   norms2   [2]  out, optional: {sum u_out^2, sum (u_out - u)^2}, reduced in
+ *                 double with a fixed order (bitwise reproducible), in the
+ *                 tiled manner of the write-conflict reductions of Sec. 3.1
+ */
+int dcp_step_fused(int dtype, const void *u, const void *f, void *u_out,
+                   int64_t nx, int64_t ny, int64_t nz, const dcp_coeffs *coeffs,
+                   int bc, double *norms2, void *ws, size_t ws_bytes,
+                   void *stream);
+
+/*
+ * The same step as the unfused single-operator program of Sec. 2.3, one
+ * kernel per statement with every temporary written to memory:
+ *     lap = Lap7(u); u3 = (u*u)*u; t1 = alpha*lap; t2 = beta*u3; t3 = t1 - t2;
+ *     t4 = gamma*f;  t5 = t3 + t4; t6 = dt*t5;     u_out = u + t6
+ * (plus one reduction kernel when norms2 is requested).  Each statement
+ * rounds once, with no contraction, so in DCP_F64 the result equals the
+ * plain serial evaluation of the same statements bit for bit.  Same
+ * arguments and rules as dcp_step_fused; the workspace holds three fields.
+ */
+int dcp_step_unfused(int dtype, const void *u, const void *f, void *u_out,
+                     int64_t nx, int64_t ny, int64_t nz,
+                     const dcp_coeffs *coeffs, int bc, double *norms2,
+                     void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * T steps in place (the time loop: a state-transition loop around one
+ * dataflow state, Sec. 2.3).
+ *   impl        DCP_FUSED or DCP_UNFUSED
+ *   u     [N]   in: u_0; out: u_T
+ *   f     [N]   in (must not overlap u)
+ *   T           >= 0 (T = 0 leaves u unchanged)
+ *   tblock      steps fused per pass over memory (temporal blocking);
+ *               1 = one pass per step.  Values > 1 need impl = DCP_FUSED.
+ *   energy [T]  out, optional: energy[t-1] = sum u_t^2, t = 1..T (double)
+ *   resid  [T]  out, optional: resid[t-1] = sqrt(sum (u_t - u_{t-1})^2)
+ *   ckpt        out, optional: ceil(T/k) consecutive fields; slot c holds
+ *               u_{c*k}, c = 0 .. ceil(T/k)-1 (must not overlap u, f or ws)
+ *   ckpt_every  k >= 1 when ckpt is given; ignored otherwise
+ * Every step uses the same kernel whether or not norms or checkpoints are
+ * requested, so u_T is bitwise identical either way.
+ */
+int dcp_run(int dtype, int impl, void *u, const void *f, int64_t nx,
+            int64_t ny, int64_t nz, const dcp_coeffs *coeffs, int bc,
+            int32_t T, int32_t tblock, double *energy, double *resid,
+            void *ckpt, int32_t ckpt_every, void *ws, size_t ws_bytes,
+            void *stream);
+
+/*
+ * Reverse-mode gradient through T fused steps, from the checkpoints that
+ * dcp_run wrote.  With J_t = I + dt*alpha*L - diag(3*beta*dt*u_t^2):
+ *     lambda_T = lam_T
+ *     lambda_t = J_t^T lambda_{t+1}                    (t = T-1 .. 0)
+ *     dL/dalpha = sum_t dt * <lambda_{t+1}, L u_t>
+ *     dL/dbeta  = sum_t -dt * <lambda_{t+1}, u_t^3>
+ * Segments [c*k, min(T, c*k+k)) are processed last to first: the states
+ * inside a segment are recomputed from its checkpoint with the forward
+ * kernel, then one fused adjoint kernel per step applies J_t^T (L is
+ * symmetric under both boundary rules, so L^T is the same 7-point gather)
+ * and accumulates the two parameter sums in double.
+ *   ckpt        [ceil(T/k) fields] in: as written by dcp_run (same T, k,
+ *               coefficients, boundary and dtype)
+ *   f      [N]  in
+ *   lam_T  [N]  in: dL/du_T
+ *   grad_u0 [N] out: dL/du_0 (must not overlap ckpt, f, lam_T or ws)
+ *   grad_ab [2] out, double: {dL/dalpha, dL/dbeta}, reduced in a fixed order,
+ *               so the result does not depend on k bit for bit
+ */
+int dcp_adjoint_run(int dtype, const void *ckpt, int32_t ckpt_every,
+                    const void *f, const void *lam_T, int64_t nx, int64_t ny,
+                    int64_t nz, const dcp_coeffs *coeffs, int bc, int32_t T,
+                    void *grad_u0, double *grad_ab, void *ws, size_t ws_bytes,
+                    void *stream);
+
+/* Static, NUL-terminated description of a dcp_status value. */
+const char *dcp_status_string(int status);
+
+/* Largest tblock accepted by dcp_run for this dtype (1 if temporal
+ * blocking is not available). */
+int32_t dcp_max_tblock(int dtype);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DCP_H */

@@ -1,0 +1,95 @@
+"""ctypes loader for libdcp.so (the C ABI declared in include/dcp.h).
+
+The library is required: there is no CPU fallback.  If it is missing the
+first call raises with instructions to build it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdcp.so")
+
+# enums of include/dcp.h
+DCP_OK = 0
+F64, F32 = 0, 1
+DIRICHLET0, PERIODIC = 0, 1
+FUSED, UNFUSED = 0, 1
+OP_STEP_FUSED, OP_STEP_UNFUSED, OP_RUN, OP_ADJOINT = 0, 1, 2, 3
+
+
+class Coeffs(ctypes.Structure):
+    """dcp_coeffs: the scalars of the program (h is the grid spacing)."""
+    _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double),
+                ("gamma", ctypes.c_double), ("h", ctypes.c_double),
+                ("dt", ctypes.c_double)]
+
+    @classmethod
+    def make(cls, c) -> "Coeffs":
+        if isinstance(c, Coeffs):
+            return c
+        return cls(float(c["alpha"]), float(c["beta"]), float(c["gamma"]),
+                   float(c["h"]), float(c["dt"]))
+
+    def as_dict(self) -> dict:
+        return dict(alpha=self.alpha, beta=self.beta, gamma=self.gamma, h=self.h, dt=self.dt)
+
+
+class DcpError(RuntimeError):
+    def __init__(self, fn: str, status: int, msg: str):
+        super().__init__(f"{fn} failed: {msg} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is not built; run `python -m paper_2107_00555_amd.build` "
+            "(or __graft_entry__.build()) first")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, c_int = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int
+    dp = ctypes.c_void_p  # device double* passed as an address
+    cp = ctypes.POINTER(Coeffs)
+    sz = ctypes.c_size_t
+    L.dcp_workspace_bytes.argtypes = [c_int, c_int, c_int, i64, i64, i64, i32, i32, i32, c_int,
+                                      ctypes.POINTER(sz)]
+    L.dcp_workspace_bytes.restype = c_int
+    step_args = [c_int, vp, vp, vp, i64, i64, i64, cp, c_int, dp, vp, sz, vp]
+    L.dcp_step_fused.argtypes = step_args
+    L.dcp_step_fused.restype = c_int
+    L.dcp_step_unfused.argtypes = step_args
+    L.dcp_step_unfused.restype = c_int
+    L.dcp_run.argtypes = [c_int, c_int, vp, vp, i64, i64, i64, cp, c_int, i32, i32, dp, dp, vp, i32,
+                          vp, sz, vp]
+    L.dcp_run.restype = c_int
+    L.dcp_adjoint_run.argtypes = [c_int, vp, i32, vp, vp, i64, i64, i64, cp, c_int, i32, vp, dp,
+                                  vp, sz, vp]
+    L.dcp_adjoint_run.restype = c_int
+    L.dcp_status_string.argtypes = [c_int]
+    L.dcp_status_string.restype = ctypes.c_char_p
+    L.dcp_max_tblock.argtypes = [c_int]
+    L.dcp_max_tblock.restype = i32
+    _lib = L
+    return L
+
+
+def check(fn: str, status: int) -> None:
+    if status != DCP_OK:
+        raise DcpError(fn, status, lib().dcp_status_string(status).decode())
+
+
+def workspace_bytes(op: int, dtype: int, nx: int, ny: int, nz: int, T: int = 0,
+                    ckpt_every: int = 1, tblock: int = 1, norms: bool = False,
+                    impl: int = FUSED) -> int:
+    out = ctypes.c_size_t(0)
+    check("dcp_workspace_bytes",
+          lib().dcp_workspace_bytes(op, dtype, impl, nx, ny, nz, T, ckpt_every, tblock,
+                                    int(bool(norms)), ctypes.byref(out)))
+    return out.value

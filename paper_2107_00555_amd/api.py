@@ -1,0 +1,149 @@
+"""torch-facing binding of libdcp: argument marshalling only.
+
+Fields are CUDA (HIP) tensors of dtype float64 or float32, contiguous, shaped
+(nz, ny, nx) -- x is the fastest axis, as in the C ABI.  Every call enqueues
+its work on the current torch stream and returns without synchronising;
+scratch memory comes from torch's allocator as a uint8 workspace tensor.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import (DIRICHLET0, F32, F64, FUSED, OP_ADJOINT, OP_RUN, OP_STEP_FUSED,
+                   OP_STEP_UNFUSED, PERIODIC, UNFUSED, Coeffs, DcpError)
+
+__all__ = ["Coeffs", "DcpError", "DIRICHLET0", "PERIODIC", "FUSED", "UNFUSED",
+           "step", "run", "adjoint_run", "workspace", "num_slots", "bc_code", "impl_code"]
+
+
+def bc_code(bc) -> int:
+    if isinstance(bc, str):
+        return {"dirichlet0": DIRICHLET0, "dirichlet": DIRICHLET0, "periodic": PERIODIC}[bc.lower()]
+    return int(bc)
+
+
+def impl_code(impl) -> int:
+    if isinstance(impl, str):
+        return {"fused": FUSED, "unfused": UNFUSED}[impl.lower()]
+    return int(impl)
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    raise TypeError(f"fields must be float64 or float32, got {t.dtype}")
+
+
+def _field(name: str, t: torch.Tensor, like: torch.Tensor | None = None) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a GPU tensor (got device {t.device})")
+    if t.dim() != 3:
+        raise ValueError(f"{name} must be 3-D shaped (nz, ny, nx), got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if like is not None:
+        if t.shape != like.shape or t.dtype != like.dtype or t.device != like.device:
+            raise ValueError(f"{name} must match shape/dtype/device of the state field")
+    return t
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device: torch.device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def workspace(nbytes: int, device) -> torch.Tensor | None:
+    if nbytes == 0:
+        return None
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def num_slots(T: int, k: int) -> int:
+    return 0 if T <= 0 else (T + k - 1) // k
+
+
+def step(u: torch.Tensor, f: torch.Tensor, coeffs, bc, impl="fused", norms: bool = False,
+         out: torch.Tensor | None = None):
+    """One step u -> u_out.  Returns (u_out, norms2) where norms2 is a float64
+    tensor {sum u_out^2, sum (u_out-u)^2} or None."""
+    u = _field("u", u)
+    f = _field("f", f, u)
+    if out is None:
+        out = torch.empty_like(u)
+    else:
+        _field("out", out, u)
+    dt = _dtype_code(u)
+    nz, ny, nx = u.shape
+    c = Coeffs.make(coeffs)
+    ic = impl_code(impl)
+    op = OP_STEP_FUSED if ic == FUSED else OP_STEP_UNFUSED
+    wsb = _lib.workspace_bytes(op, dt, nx, ny, nz, norms=norms)
+    ws = workspace(wsb, u.device)
+    n2 = torch.empty(2, dtype=torch.float64, device=u.device) if norms else None
+    fn = _lib.lib().dcp_step_fused if ic == FUSED else _lib.lib().dcp_step_unfused
+    _lib.check(fn.__name__, fn(dt, _ptr(u), _ptr(f), _ptr(out), nx, ny, nz, ctypes.byref(c),
+                               bc_code(bc), _ptr(n2), _ptr(ws), wsb, _stream(u.device)))
+    return out, n2
+
+
+def run(u: torch.Tensor, f: torch.Tensor, coeffs, T: int, bc, impl="fused", tblock: int = 1,
+        norms: bool = True, ckpt_every: int = 0, ws: torch.Tensor | None = None,
+        ckpt: torch.Tensor | None = None):
+    """T steps in place on u.  Returns a dict with 'energy' and 'resid'
+    (float64 [T] tensors, or None) and 'ckpt' (tensor of ceil(T/k) fields
+    shaped (slots, nz, ny, nx), or None when ckpt_every == 0)."""
+    u = _field("u", u)
+    f = _field("f", f, u)
+    dt = _dtype_code(u)
+    nz, ny, nx = u.shape
+    c = Coeffs.make(coeffs)
+    ic = impl_code(impl)
+    wsb = _lib.workspace_bytes(OP_RUN, dt, nx, ny, nz, T=T, tblock=tblock, norms=norms, impl=ic)
+    if ws is None or ws.numel() < wsb:
+        ws = workspace(wsb, u.device)
+    energy = torch.empty(max(T, 0), dtype=torch.float64, device=u.device) if norms else None
+    resid = torch.empty(max(T, 0), dtype=torch.float64, device=u.device) if norms else None
+    if ckpt_every and ckpt is None:
+        ckpt = torch.empty((num_slots(T, ckpt_every), nz, ny, nx), dtype=u.dtype, device=u.device)
+    elif not ckpt_every:
+        ckpt = None
+    _lib.check("dcp_run", _lib.lib().dcp_run(
+        dt, ic, _ptr(u), _ptr(f), nx, ny, nz, ctypes.byref(c), bc_code(bc), int(T), int(tblock),
+        _ptr(energy), _ptr(resid), _ptr(ckpt), int(ckpt_every), _ptr(ws), wsb, _stream(u.device)))
+    return {"energy": energy, "resid": resid, "ckpt": ckpt}
+
+
+def adjoint_run(ckpt: torch.Tensor | None, ckpt_every: int, f: torch.Tensor, lam_T: torch.Tensor,
+                coeffs, T: int, bc, ws: torch.Tensor | None = None,
+                grad_u0: torch.Tensor | None = None):
+    """Gradient through T fused steps from dcp_run's checkpoints.
+    Returns (dL/du0, float64 tensor [dL/dalpha, dL/dbeta])."""
+    lam_T = _field("lam_T", lam_T)
+    f = _field("f", f, lam_T)
+    dt = _dtype_code(lam_T)
+    nz, ny, nx = lam_T.shape
+    if T > 0 and lam_T.numel() > 0:
+        if ckpt is None or ckpt.dtype != lam_T.dtype or not ckpt.is_contiguous() \
+                or ckpt.numel() < num_slots(T, ckpt_every) * lam_T.numel():
+            raise ValueError("ckpt must hold ceil(T/ckpt_every) contiguous fields of the state dtype")
+    c = Coeffs.make(coeffs)
+    wsb = _lib.workspace_bytes(OP_ADJOINT, dt, nx, ny, nz, T=T, ckpt_every=ckpt_every)
+    if ws is None or ws.numel() < wsb:
+        ws = workspace(wsb, lam_T.device)
+    if grad_u0 is None:
+        grad_u0 = torch.empty_like(lam_T)
+    gab = torch.empty(2, dtype=torch.float64, device=lam_T.device)
+    _lib.check("dcp_adjoint_run", _lib.lib().dcp_adjoint_run(
+        dt, _ptr(ckpt), int(ckpt_every), _ptr(f), _ptr(lam_T), nx, ny, nz, ctypes.byref(c),
+        bc_code(bc), int(T), _ptr(grad_u0), _ptr(gab), _ptr(ws), wsb, _stream(lam_T.device)))
+    return grad_u0, gab

@@ -1,0 +1,550 @@
+// dcp_api.cpp -- C ABI of libdcp (declared in include/dcp.h): argument
+// checks, workspace layout, tile choice and the host drivers of the time
+// loop and of the checkpointed adjoint.  All device work is enqueued on the
+// caller's stream; nothing here synchronises or allocates device memory.
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <initializer_list>
+
+#include "dcp.h"
+#include "dcp_internal.h"
+
+using namespace dcp;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Geo {
+    int64_t nx = 0, ny = 0, nz = 0, n = 0;
+    size_t esz = 8;
+    size_t bytes() const { return (size_t)n * esz; }
+};
+
+int check_geo(int dtype, int64_t nx, int64_t ny, int64_t nz, Geo *g) {
+    if (dtype != DCP_F64 && dtype != DCP_F32) return DCP_E_DTYPE;
+    if (nx < 0 || ny < 0 || nz < 0) return DCP_E_SHAPE;
+    const int64_t ext_lim = (int64_t)1 << 30;
+    if (nx > ext_lim || ny > ext_lim || nz > ext_lim) return DCP_E_SHAPE;
+    g->esz = dtype == DCP_F64 ? 8 : 4;
+    g->nx = nx;
+    g->ny = ny;
+    g->nz = nz;
+    g->n = 0;
+    if (nx && ny && nz) {
+        const int64_t lim = ((int64_t)1 << 60) / (int64_t)g->esz;
+        if (nx > lim / ny) return DCP_E_SHAPE;
+        const int64_t nxy = nx * ny;
+        if (nxy > lim / nz) return DCP_E_SHAPE;
+        g->n = nxy * nz;
+    }
+    return DCP_OK;
+}
+
+int check_coeffs(const dcp_coeffs *c) {
+    if (!c) return DCP_E_NULL;
+    const double v[5] = {c->alpha, c->beta, c->gamma, c->h, c->dt};
+    for (double x : v)
+        if (!std::isfinite(x)) return DCP_E_ARG;
+    if (!(c->h > 0.0)) return DCP_E_ARG;
+    return DCP_OK;
+}
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
+    if (!a || !b || na == 0 || nb == 0) return false;
+    const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+    return a0 < b0 + nb && b0 < a0 + na;
+}
+
+// ------------------------------------------------------------- tile choice
+int env_int(const char *name, int def) {
+    const char *s = std::getenv(name);
+    if (!s || !*s) return def;
+    return std::atoi(s);
+}
+
+Tile make_tile(const Geo &g, int vec, int shape, int zc) {
+    Tile t{};
+    const Shape s = shape_at(shape);
+    t.vec = vec;
+    t.bxw = s.bxw;
+    t.by = s.by;
+    t.ry = s.ry;
+    t.zc = zc;
+    const int64_t tx = (g.nx + (int64_t)64 * s.bxw * vec - 1) / ((int64_t)64 * s.bxw * vec);
+    const int64_t ty = (g.ny + (int64_t)s.by * s.ry - 1) / ((int64_t)s.by * s.ry);
+    const int64_t tz = (g.nz + zc - 1) / zc;
+    const int64_t nb = tx * ty * tz;
+    t.tiles_x = (int)tx;
+    t.tiles_y = (int)ty;
+    t.tiles_z = (int)tz;
+    t.nblk = nb > INT32_MAX / 1024 ? -1 : (int)nb;
+    return t;
+}
+
+// Tile for one field operand layout.  The default is tuned for the 512^3
+// class of grids; DCP_TILE_SHAPE / DCP_TILE_ZC override it for tuning runs.
+Tile pick_tile(int dtype, const Geo &g, bool vec_ok) {
+    const int wide = dtype == DCP_F64 ? 2 : 4;
+    const int vec = vec_ok ? wide : 1;
+    int shape = env_int("DCP_TILE_SHAPE", 0);
+    if (shape < 0 || shape >= num_shapes()) shape = 0;
+    int zc = env_int("DCP_TILE_ZC", 0);
+    if (zc <= 0) {
+        // enough workgroups to fill 256 CUs several times over, but long
+        // z-runs so the two extra planes per run stay a small overhead
+        zc = 64;
+        while (zc > 8 && make_tile(g, vec, shape, zc).nblk >= 0 &&
+               make_tile(g, vec, shape, zc).nblk < 2048)
+            zc /= 2;
+    }
+    if (g.nz > 0 && zc > g.nz) zc = (int)g.nz;
+    if (zc < 1) zc = 1;
+    return make_tile(g, vec, shape, zc);
+}
+
+// Largest workgroup count over both vector widths (workspace sizing must not
+// depend on pointer alignment).
+int max_blocks(int dtype, const Geo &g) {
+    if (g.n == 0) return 0;
+    const Tile a = pick_tile(dtype, g, true), b = pick_tile(dtype, g, false);
+    if (a.nblk < 0 || b.nblk < 0) return -1;
+    return a.nblk > b.nblk ? a.nblk : b.nblk;
+}
+
+// ---------------------------------------------------------- workspace layout
+struct StepWs {
+    size_t temps = 0;     // offset of 3 temporaries (unfused)
+    size_t partials = 0;  // offset of partial sums
+    size_t total = 0;
+};
+
+int layout_step(int dtype, int impl, const Geo &g, bool norms, StepWs *w) {
+    size_t off = 0;
+    if (impl == DCP_UNFUSED && g.n > 0) {
+        w->temps = off;
+        off += 3 * align_up(g.bytes());
+    }
+    if (norms && g.n > 0) {
+        const int nb = impl == DCP_UNFUSED ? ew_norm_blocks(g.n) : max_blocks(dtype, g);
+        if (nb < 0) return DCP_E_SHAPE;
+        w->partials = off;
+        off += align_up((size_t)nb * 2 * sizeof(double));
+    }
+    w->total = off;
+    return DCP_OK;
+}
+
+struct RunWs {
+    size_t field = 0;     // ping-pong field
+    size_t temps = 0;     // unfused temporaries
+    size_t partials = 0;  // [T][nblk][2]
+    int nblk = 0;
+    size_t total = 0;
+};
+
+int layout_run(int dtype, int impl, const Geo &g, int32_t T, bool norms, RunWs *w) {
+    size_t off = 0;
+    if (g.n == 0 || T == 0) {
+        w->total = 0;
+        return DCP_OK;
+    }
+    w->field = off;
+    off += align_up(g.bytes());
+    if (impl == DCP_UNFUSED) {
+        w->temps = off;
+        off += 3 * align_up(g.bytes());
+    }
+    if (norms) {
+        const int nb = impl == DCP_UNFUSED ? ew_norm_blocks(g.n) : max_blocks(dtype, g);
+        if (nb < 0) return DCP_E_SHAPE;
+        w->nblk = nb;
+        w->partials = off;
+        off += align_up((size_t)T * nb * 2 * sizeof(double));
+    }
+    w->total = off;
+    return DCP_OK;
+}
+
+struct AdjWs {
+    size_t lam = 0;       // 2 fields
+    size_t seg = 0;       // k-1 fields
+    size_t partials = 0;  // [T][nblk][2]
+    size_t sums = 0;      // [T][2]
+    int nblk = 0;
+    size_t total = 0;
+};
+
+int layout_adj(int dtype, const Geo &g, int32_t T, int32_t k, AdjWs *w) {
+    size_t off = 0;
+    if (T == 0) {
+        w->total = 0;
+        return DCP_OK;
+    }
+    if (g.n > 0) {
+        const int nb = max_blocks(dtype, g);
+        if (nb < 0) return DCP_E_SHAPE;
+        w->nblk = nb;
+        w->lam = off;
+        off += 2 * align_up(g.bytes());
+        w->seg = off;
+        const int32_t kk = k < T ? k : T;
+        off += (size_t)(kk - 1) * align_up(g.bytes());
+        w->partials = off;
+        off += align_up((size_t)T * nb * 2 * sizeof(double));
+    }
+    w->sums = off;
+    off += align_up((size_t)T * 2 * sizeof(double));
+    w->total = off;
+    return DCP_OK;
+}
+
+int check_ws(const void *ws, size_t ws_bytes, size_t need) {
+    if (need == 0) return DCP_OK;
+    if (ws_bytes < need) return DCP_E_WORKSPACE;
+    if (!ws) return DCP_E_NULL;
+    return DCP_OK;
+}
+
+char *at(void *base, size_t off) { return static_cast<char *>(base) + off; }
+
+int hip_status(hipError_t e) { return e == hipSuccess ? DCP_OK : DCP_E_HIP; }
+
+#define DCP_TRY(expr)                            \
+    do {                                         \
+        hipError_t e_ = (expr);                  \
+        if (e_ != hipSuccess) return DCP_E_HIP;  \
+    } while (0)
+
+StencilArgs fwd_args(const Geo &g, const dcp_coeffs &c, const Tile &t, const void *u, const void *f,
+                     void *out, double *partials) {
+    StencilArgs a{};
+    a.s = u;
+    a.q = f;
+    a.out = out;
+    a.partials = partials;
+    a.nx = g.nx;
+    a.ny = g.ny;
+    a.nz = g.nz;
+    a.c0 = c.dt * c.alpha / (c.h * c.h);
+    a.c1 = c.dt * c.beta;
+    a.c2 = c.dt * c.gamma;
+    a.tiles_x = t.tiles_x;
+    a.tiles_y = t.tiles_y;
+    a.zc = t.zc;
+    a.nblk = t.nblk;
+    return a;
+}
+
+// One fused step u -> out (partials may be null).
+hipError_t fused_step(int dtype, int bc, const Geo &g, const dcp_coeffs &c, const Tile &t, const void *u,
+                      const void *f, void *out, double *partials, hipStream_t st) {
+    const StencilArgs a = fwd_args(g, c, t, u, f, out, partials);
+    return launch_stencil(dtype, SOP_FWD, bc, partials != nullptr, t, a, st);
+}
+
+// One unfused step (the single-operator statements), temporaries in tmp[3].
+hipError_t unfused_step(int dtype, int bc, const Geo &g, const dcp_coeffs &c, const Tile &t, bool vec_ok,
+                        const void *u, const void *f, void *out, void *const tmp[3], double *partials,
+                        hipStream_t st) {
+    void *A = tmp[0], *B = tmp[1], *C = tmp[2];
+    StencilArgs a{};
+    a.s = u;
+    a.q = nullptr;
+    a.out = A;
+    a.partials = nullptr;
+    a.nx = g.nx;
+    a.ny = g.ny;
+    a.nz = g.nz;
+    a.c0 = c.h * c.h;
+    a.tiles_x = t.tiles_x;
+    a.tiles_y = t.tiles_y;
+    a.zc = t.zc;
+    a.nblk = t.nblk;
+    hipError_t e;
+    if ((e = launch_stencil(dtype, SOP_LAP, bc, false, t, a, st)) != hipSuccess) return e;  // lap = Lap7(u)  -> A
+    if ((e = launch_ew(dtype, EW_POW3, u, nullptr, B, 0.0, g.n, vec_ok, st))) return e;     // u3 = (u*u)*u  -> B
+    if ((e = launch_ew(dtype, EW_SCALE, A, nullptr, C, c.alpha, g.n, vec_ok, st))) return e;  // t1 = alpha*lap -> C
+    if ((e = launch_ew(dtype, EW_SCALE, B, nullptr, A, c.beta, g.n, vec_ok, st))) return e;   // t2 = beta*u3  -> A
+    if ((e = launch_ew(dtype, EW_SUB, C, A, B, 0.0, g.n, vec_ok, st))) return e;              // t3 = t1 - t2  -> B
+    if ((e = launch_ew(dtype, EW_SCALE, f, nullptr, C, c.gamma, g.n, vec_ok, st))) return e;  // t4 = gamma*f  -> C
+    if ((e = launch_ew(dtype, EW_ADD, B, C, A, 0.0, g.n, vec_ok, st))) return e;              // t5 = t3 + t4  -> A
+    if ((e = launch_ew(dtype, EW_SCALE, A, nullptr, B, c.dt, g.n, vec_ok, st))) return e;     // t6 = dt*t5    -> B
+    if ((e = launch_ew(dtype, EW_ADD, u, B, out, 0.0, g.n, vec_ok, st))) return e;            // u' = u + t6
+    if (partials) return launch_ew_norms(dtype, out, u, partials, g.n, vec_ok, st);
+    return hipSuccess;
+}
+
+bool vec_ok_for(int dtype, const Geo &g, std::initializer_list<const void *> ptrs) {
+    const int wide = dtype == DCP_F64 ? 2 : 4;
+    if (g.nx % wide != 0) return false;
+    for (const void *p : ptrs)
+        if (p && !aligned16(p)) return false;
+    return true;
+}
+
+int step_common(int impl, int dtype, const void *u, const void *f, void *u_out, int64_t nx, int64_t ny,
+                int64_t nz, const dcp_coeffs *coeffs, int bc, double *norms2, void *ws, size_t ws_bytes,
+                void *stream) {
+    Geo g;
+    int rc = check_geo(dtype, nx, ny, nz, &g);
+    if (rc) return rc;
+    if (bc != DCP_DIRICHLET0 && bc != DCP_PERIODIC) return DCP_E_BC;
+    if ((rc = check_coeffs(coeffs))) return rc;
+    if (g.n > 0 && (!u || !f || !u_out)) return DCP_E_NULL;
+    StepWs w;
+    if ((rc = layout_step(dtype, impl, g, norms2 != nullptr, &w))) return rc;
+    if ((rc = check_ws(ws, ws_bytes, w.total))) return rc;
+    const size_t fb = g.bytes();
+    if (overlaps(u_out, fb, u, fb) || overlaps(u_out, fb, f, fb)) return DCP_E_ALIAS;
+    if (overlaps(ws, w.total, u, fb) || overlaps(ws, w.total, f, fb) || overlaps(ws, w.total, u_out, fb))
+        return DCP_E_ALIAS;
+    if (norms2 && (overlaps(norms2, 16, u, fb) || overlaps(norms2, 16, f, fb) ||
+                   overlaps(norms2, 16, u_out, fb) || overlaps(norms2, 16, ws, w.total)))
+        return DCP_E_ALIAS;
+
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (g.n == 0) return norms2 ? hip_status(launch_zero(norms2, 2, st)) : DCP_OK;
+
+    double *partials = norms2 ? reinterpret_cast<double *>(at(ws, w.partials)) : nullptr;
+    if (impl == DCP_FUSED) {
+        const Tile t = pick_tile(dtype, g, vec_ok_for(dtype, g, {u, f, u_out}));
+        DCP_TRY(fused_step(dtype, bc, g, *coeffs, t, u, f, u_out, partials, st));
+        if (norms2) DCP_TRY(launch_finalize(partials, t.nblk, 1, norms2, nullptr, 0, st));
+    } else {
+        void *tmp[3] = {at(ws, w.temps), at(ws, w.temps + align_up(fb)), at(ws, w.temps + 2 * align_up(fb))};
+        const bool vok = vec_ok_for(dtype, g, {u, f, u_out, tmp[0], tmp[1], tmp[2]});
+        const Tile t = pick_tile(dtype, g, vok);
+        DCP_TRY(unfused_step(dtype, bc, g, *coeffs, t, vok, u, f, u_out, tmp, partials, st));
+        if (norms2) DCP_TRY(launch_finalize(partials, ew_norm_blocks(g.n), 1, norms2, nullptr, 0, st));
+    }
+    return DCP_OK;
+}
+
+int32_t num_slots(int32_t T, int32_t k) { return T <= 0 ? 0 : (T + k - 1) / k; }
+
+}  // namespace
+
+extern "C" {
+
+const char *dcp_status_string(int status) {
+    switch (status) {
+        case DCP_OK: return "ok";
+        case DCP_E_NULL: return "a required pointer is NULL";
+        case DCP_E_SHAPE: return "invalid grid shape (negative extent or size overflow)";
+        case DCP_E_DTYPE: return "invalid dtype (expected DCP_F64 or DCP_F32)";
+        case DCP_E_BC: return "invalid boundary (expected DCP_DIRICHLET0 or DCP_PERIODIC)";
+        case DCP_E_ARG: return "invalid argument (T, ckpt_every, tblock, h, impl, op or a non-finite coefficient)";
+        case DCP_E_WORKSPACE: return "workspace too small";
+        case DCP_E_ALIAS: return "an output overlaps an input";
+        case DCP_E_HIP: return "HIP launch or copy failed";
+        default: return "unknown status";
+    }
+}
+
+int32_t dcp_max_tblock(int dtype) {
+    (void)dtype;
+    return 1;
+}
+
+int dcp_workspace_bytes(int op, int dtype, int impl, int64_t nx, int64_t ny, int64_t nz, int32_t T,
+                        int32_t ckpt_every, int32_t tblock, int norms, size_t *bytes) {
+    if (!bytes) return DCP_E_NULL;
+    Geo g;
+    int rc = check_geo(dtype, nx, ny, nz, &g);
+    if (rc) return rc;
+    switch (op) {
+        case DCP_OP_STEP_FUSED:
+        case DCP_OP_STEP_UNFUSED: {
+            StepWs w;
+            if ((rc = layout_step(dtype, op == DCP_OP_STEP_FUSED ? DCP_FUSED : DCP_UNFUSED, g, norms != 0, &w)))
+                return rc;
+            *bytes = w.total;
+            return DCP_OK;
+        }
+        case DCP_OP_RUN: {
+            if (impl != DCP_FUSED && impl != DCP_UNFUSED) return DCP_E_ARG;
+            if (T < 0 || tblock < 1 || tblock > dcp_max_tblock(dtype)) return DCP_E_ARG;
+            RunWs w;
+            if ((rc = layout_run(dtype, impl, g, T, norms != 0, &w))) return rc;
+            *bytes = w.total;
+            return DCP_OK;
+        }
+        case DCP_OP_ADJOINT: {
+            if (T < 0 || ckpt_every < 1) return DCP_E_ARG;
+            AdjWs w;
+            if ((rc = layout_adj(dtype, g, T, ckpt_every, &w))) return rc;
+            *bytes = w.total;
+            return DCP_OK;
+        }
+        default: return DCP_E_ARG;
+    }
+}
+
+int dcp_step_fused(int dtype, const void *u, const void *f, void *u_out, int64_t nx, int64_t ny, int64_t nz,
+                   const dcp_coeffs *coeffs, int bc, double *norms2, void *ws, size_t ws_bytes, void *stream) {
+    return step_common(DCP_FUSED, dtype, u, f, u_out, nx, ny, nz, coeffs, bc, norms2, ws, ws_bytes, stream);
+}
+
+int dcp_step_unfused(int dtype, const void *u, const void *f, void *u_out, int64_t nx, int64_t ny, int64_t nz,
+                     const dcp_coeffs *coeffs, int bc, double *norms2, void *ws, size_t ws_bytes, void *stream) {
+    return step_common(DCP_UNFUSED, dtype, u, f, u_out, nx, ny, nz, coeffs, bc, norms2, ws, ws_bytes, stream);
+}
+
+int dcp_run(int dtype, int impl, void *u, const void *f, int64_t nx, int64_t ny, int64_t nz,
+            const dcp_coeffs *coeffs, int bc, int32_t T, int32_t tblock, double *energy, double *resid,
+            void *ckpt, int32_t ckpt_every, void *ws, size_t ws_bytes, void *stream) {
+    Geo g;
+    int rc = check_geo(dtype, nx, ny, nz, &g);
+    if (rc) return rc;
+    if (bc != DCP_DIRICHLET0 && bc != DCP_PERIODIC) return DCP_E_BC;
+    if ((rc = check_coeffs(coeffs))) return rc;
+    if (impl != DCP_FUSED && impl != DCP_UNFUSED) return DCP_E_ARG;
+    if (T < 0 || tblock < 1 || tblock > dcp_max_tblock(dtype)) return DCP_E_ARG;
+    if (tblock > 1 && impl != DCP_FUSED) return DCP_E_ARG;
+    if (ckpt && ckpt_every < 1) return DCP_E_ARG;
+    if (g.n > 0 && (!u || !f)) return DCP_E_NULL;
+    const bool norms = energy || resid;
+    RunWs w;
+    if ((rc = layout_run(dtype, impl, g, T, norms, &w))) return rc;
+    if ((rc = check_ws(ws, ws_bytes, w.total))) return rc;
+    const size_t fb = g.bytes();
+    const int32_t nslots = ckpt ? num_slots(T, ckpt_every) : 0;
+    const size_t cb = (size_t)nslots * fb;
+    const size_t nb = (size_t)(T > 0 ? T : 0) * sizeof(double);
+    if (overlaps(u, fb, f, fb)) return DCP_E_ALIAS;
+    if (overlaps(ws, w.total, u, fb) || overlaps(ws, w.total, f, fb)) return DCP_E_ALIAS;
+    if (overlaps(ckpt, cb, u, fb) || overlaps(ckpt, cb, f, fb) || overlaps(ckpt, cb, ws, w.total))
+        return DCP_E_ALIAS;
+    for (const double *o : {energy, resid})
+        if (o && (overlaps(o, nb, u, fb) || overlaps(o, nb, f, fb) || overlaps(o, nb, ws, w.total) ||
+                  overlaps(o, nb, ckpt, cb)))
+            return DCP_E_ALIAS;
+    if (energy && resid && overlaps(energy, nb, resid, nb)) return DCP_E_ALIAS;
+
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (T == 0) return DCP_OK;
+    if (g.n == 0) {
+        if (energy) DCP_TRY(launch_zero(energy, T, st));
+        if (resid) DCP_TRY(launch_zero(resid, T, st));
+        return DCP_OK;
+    }
+
+    void *buf = at(ws, w.field);
+    void *tmp[3] = {nullptr, nullptr, nullptr};
+    if (impl == DCP_UNFUSED)
+        for (int i = 0; i < 3; ++i) tmp[i] = at(ws, w.temps + i * align_up(fb));
+    auto slot = [&](int32_t c) { return static_cast<void *>(static_cast<char *>(ckpt) + (size_t)c * fb); };
+    bool vok = vec_ok_for(dtype, g, {u, f, buf, tmp[0], tmp[1], tmp[2]});
+    for (int32_t c = 0; c < nslots; ++c) vok = vok && aligned16(slot(c));
+    const Tile t = pick_tile(dtype, g, vok);
+    const int nblk_red = impl == DCP_UNFUSED ? ew_norm_blocks(g.n) : t.nblk;
+    double *partials = norms ? reinterpret_cast<double *>(at(ws, w.partials)) : nullptr;
+
+    if (nslots > 0) DCP_TRY(hipMemcpyAsync(slot(0), u, fb, hipMemcpyDeviceToDevice, st));
+    const void *cur = u;
+    for (int32_t s = 0; s < T; ++s) {
+        void *nxt;
+        const int32_t s1 = s + 1;
+        if (nslots > 0 && s1 % ckpt_every == 0 && s1 / ckpt_every < nslots)
+            nxt = slot(s1 / ckpt_every);
+        else
+            nxt = (cur == u) ? buf : u;
+        double *p = partials ? partials + (size_t)s * nblk_red * 2 : nullptr;
+        if (impl == DCP_FUSED)
+            DCP_TRY(fused_step(dtype, bc, g, *coeffs, t, cur, f, nxt, p, st));
+        else
+            DCP_TRY(unfused_step(dtype, bc, g, *coeffs, t, vok, cur, f, nxt, tmp, p, st));
+        cur = nxt;
+    }
+    if (cur != u) DCP_TRY(hipMemcpyAsync(u, cur, fb, hipMemcpyDeviceToDevice, st));
+    if (norms) DCP_TRY(launch_finalize(partials, nblk_red, T, energy, resid, 1, st));
+    return DCP_OK;
+}
+
+int dcp_adjoint_run(int dtype, const void *ckpt, int32_t ckpt_every, const void *f, const void *lam_T, int64_t nx,
+                    int64_t ny, int64_t nz, const dcp_coeffs *coeffs, int bc, int32_t T, void *grad_u0,
+                    double *grad_ab, void *ws, size_t ws_bytes, void *stream) {
+    Geo g;
+    int rc = check_geo(dtype, nx, ny, nz, &g);
+    if (rc) return rc;
+    if (bc != DCP_DIRICHLET0 && bc != DCP_PERIODIC) return DCP_E_BC;
+    if ((rc = check_coeffs(coeffs))) return rc;
+    if (T < 0 || ckpt_every < 1) return DCP_E_ARG;
+    if (!grad_ab) return DCP_E_NULL;
+    if (g.n > 0 && (!f || !lam_T || !grad_u0 || (T > 0 && !ckpt))) return DCP_E_NULL;
+    AdjWs w;
+    if ((rc = layout_adj(dtype, g, T, ckpt_every, &w))) return rc;
+    if ((rc = check_ws(ws, ws_bytes, w.total))) return rc;
+    const size_t fb = g.bytes();
+    const int32_t nslots = num_slots(T, ckpt_every);
+    const size_t cb = (size_t)nslots * fb;
+    if (overlaps(grad_u0, fb, ckpt, cb) || overlaps(grad_u0, fb, f, fb) || overlaps(grad_u0, fb, lam_T, fb) ||
+        overlaps(grad_u0, fb, ws, w.total))
+        return DCP_E_ALIAS;
+    if (overlaps(ws, w.total, ckpt, cb) || overlaps(ws, w.total, f, fb) || overlaps(ws, w.total, lam_T, fb))
+        return DCP_E_ALIAS;
+    if (overlaps(grad_ab, 16, grad_u0, fb) || overlaps(grad_ab, 16, ws, w.total) || overlaps(grad_ab, 16, ckpt, cb))
+        return DCP_E_ALIAS;
+
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (T == 0 || g.n == 0) {
+        if (g.n > 0) DCP_TRY(hipMemcpyAsync(grad_u0, lam_T, fb, hipMemcpyDeviceToDevice, st));
+        DCP_TRY(launch_zero(grad_ab, 2, st));
+        return DCP_OK;
+    }
+
+    void *lam[2] = {at(ws, w.lam), at(ws, w.lam + align_up(fb))};
+    const int32_t kk = ckpt_every < T ? ckpt_every : T;
+    auto seg = [&](int32_t j) { return static_cast<void *>(at(ws, w.seg + (size_t)j * align_up(fb))); };
+    auto slot = [&](int32_t c) { return static_cast<const void *>(static_cast<const char *>(ckpt) + (size_t)c * fb); };
+    bool vok = vec_ok_for(dtype, g, {f, lam_T, grad_u0, lam[0], lam[1]});
+    for (int32_t c = 0; c < nslots; ++c) vok = vok && aligned16(slot(c));
+    for (int32_t j = 0; j + 1 < kk; ++j) vok = vok && aligned16(seg(j));
+    const Tile t = pick_tile(dtype, g, vok);
+    double *partials = reinterpret_cast<double *>(at(ws, w.partials));
+    double *sums = reinterpret_cast<double *>(at(ws, w.sums));
+    const dcp_coeffs &c = *coeffs;
+
+    StencilArgs aa{};
+    aa.nx = g.nx;
+    aa.ny = g.ny;
+    aa.nz = g.nz;
+    aa.c0 = c.dt * c.alpha / (c.h * c.h);
+    aa.c1 = 3.0 * c.dt * c.beta;
+    aa.tiles_x = t.tiles_x;
+    aa.tiles_y = t.tiles_y;
+    aa.zc = t.zc;
+    aa.nblk = t.nblk;
+
+    const void *lcur = lam_T;
+    for (int32_t cs = nslots - 1; cs >= 0; --cs) {
+        const int32_t t0 = cs * ckpt_every;
+        const int32_t t1 = (t0 + ckpt_every < T) ? t0 + ckpt_every : T;
+        // recompute the states u_{t0+1} .. u_{t1-1} of this segment
+        const void *prev = slot(cs);
+        for (int32_t j = 1; j < t1 - t0; ++j) {
+            DCP_TRY(fused_step(dtype, bc, g, c, t, prev, f, seg(j - 1), nullptr, st));
+            prev = seg(j - 1);
+        }
+        for (int32_t s = t1 - 1; s >= t0; --s) {
+            const void *ut = (s == t0) ? slot(cs) : static_cast<const void *>(seg(s - t0 - 1));
+            void *out = (s == 0) ? grad_u0 : (lcur == lam[0] ? lam[1] : lam[0]);
+            aa.s = lcur;
+            aa.q = ut;
+            aa.out = out;
+            aa.partials = partials + (size_t)s * t.nblk * 2;
+            DCP_TRY(launch_stencil(dtype, SOP_ADJ, bc, true, t, aa, st));
+            lcur = out;
+        }
+    }
+    DCP_TRY(launch_finalize(partials, t.nblk, T, sums, nullptr, 2, st));
+    DCP_TRY(launch_grad_finalize(sums, T, c.dt / (c.h * c.h), -c.dt, grad_ab, st));
+    return DCP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,75 @@
+// dcp_internal.h -- launch interface between the host driver (dcp_api.cpp)
+// and the gfx950 kernels (dcp_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace dcp {
+
+enum StencilOp : int {
+    SOP_FWD = 0,  // u' = u + c0*(S6 - 6u) - c1*u^3 + c2*f      (S6 = sum of 6 neighbours)
+    SOP_ADJ = 1,  // l' = l + c0*(S6 - 6l) - c1*u^2*l ; sums (S6-6l)*u and l*u^3
+    SOP_LAP = 2,  // lap = (((((xm+xp)+ym)+yp)+zm)+zp - 6u) / c0, one rounding per op
+};
+
+// Tile of one workgroup: 64*bxw*vec points along x (bxw waves side by side),
+// by*ry rows along y (by waves stacked, ry rows per lane), zc planes along z.
+struct Tile {
+    int vec;  // elements per lane along x (16-byte vectors, or 1)
+    int bxw, by, ry;
+    int zc;
+    int tiles_x, tiles_y, tiles_z;
+    int nblk;
+};
+
+struct StencilArgs {
+    const void *s;       // stencil operand (u, or lambda_{t+1})
+    const void *q;       // point operand (f, or u_t); unused by SOP_LAP
+    void *out;           // output field
+    double *partials;    // [nblk][2] per-workgroup sums, or null
+    int64_t nx, ny, nz;
+    double c0, c1, c2;
+    int tiles_x, tiles_y, zc, nblk;
+};
+
+// Tile shapes compiled into the library, in preference order.
+struct Shape {
+    int bxw, by, ry;
+};
+int num_shapes();
+Shape shape_at(int i);
+
+// Launches the z-marching stencil kernel.  `reduce` selects the variant
+// that writes per-workgroup double sums to a.partials.
+hipError_t launch_stencil(int dtype, int op, int bc, bool reduce, const Tile &t,
+                          const StencilArgs &a, hipStream_t stream);
+
+// Element-wise statements of the unfused program.
+enum EwOp : int { EW_POW3 = 0, EW_SCALE = 1, EW_SUB = 2, EW_ADD = 3 };
+hipError_t launch_ew(int dtype, int op, const void *x, const void *y, void *o,
+                     double a, int64_t n, bool vec_ok, hipStream_t stream);
+
+// Per-workgroup sums {sum o^2, sum (o - u)^2} for the unfused program.
+int ew_norm_blocks(int64_t n);
+hipError_t launch_ew_norms(int dtype, const void *o, const void *u,
+                           double *partials, int64_t n, bool vec_ok,
+                           hipStream_t stream);
+
+// Fixed-order reduction of [nsteps][nblk][2] partials.
+//   mode 0: out0[0] = sum k=0, out0[1] = sum k=1          (one step)
+//   mode 1: out0[s] = sum k=0, out1[s] = sqrt(sum k=1)   (either may be null)
+//   mode 2: out0[2s+k] = sum k                           (per-step sums)
+hipError_t launch_finalize(const double *partials, int nblk, int nsteps,
+                           double *out0, double *out1, int mode,
+                           hipStream_t stream);
+
+// grad[0] = s0 * sum_t sums[2t], grad[1] = s1 * sum_t sums[2t+1] (t ascending).
+hipError_t launch_grad_finalize(const double *sums, int nsteps, double s0,
+                                double s1, double *grad, hipStream_t stream);
+
+// dst[0..n) = 0 (doubles), a kernel rather than a memset node.
+hipError_t launch_zero(double *dst, int64_t n, hipStream_t stream);
+
+}  // namespace dcp

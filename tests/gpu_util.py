@@ -1,0 +1,51 @@
+"""Shared helpers for the GPU tests (test-side only)."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import torch
+
+DEV = torch.device("cuda:0")
+BASE = dict(alpha=1.0, beta=0.1, gamma=0.5, h=1.0, dt=0.1)
+
+
+def say(*a):
+    """Name the case before a GPU step, flushed, so a crash still shows it."""
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(a: np.ndarray, dtype=torch.float64) -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device=DEV, dtype=dtype).contiguous()
+
+
+def to_host(t: torch.Tensor) -> np.ndarray:
+    return t.detach().to("cpu", torch.float64).numpy()
+
+
+def f32_round(a: np.ndarray) -> np.ndarray:
+    """Round to float32 (nearest even) and widen back exactly."""
+    return a.astype(np.float32).astype(np.float64)
+
+
+def normwise(a: np.ndarray, b: np.ndarray) -> float:
+    """max|a-b| / max|b|: the error measure used for fields (pointwise
+    relative error is unbounded where the field crosses zero)."""
+    den = float(np.max(np.abs(b))) if b.size else 0.0
+    return float(np.max(np.abs(a - b))) / den if den > 0 else float(np.max(np.abs(a - b), initial=0.0))
+
+
+def rand_fields(shape, seed):
+    nx, ny, nz = shape
+    r = np.random.default_rng(seed)
+    return r.uniform(-1, 1, (nz, ny, nx)), r.uniform(-1, 1, (nz, ny, nx))
+
+
+def misaligned_like(a: torch.Tensor) -> torch.Tensor:
+    """A contiguous copy of a whose data pointer is NOT 16-byte aligned."""
+    buf = torch.empty(a.numel() + 1, dtype=a.dtype, device=a.device)
+    v = buf[1:].view(a.shape)
+    v.copy_(a)
+    assert v.data_ptr() % 16 != 0
+    return v

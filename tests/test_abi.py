@@ -1,0 +1,161 @@
+"""libdcp C ABI, host side: the library loads, exports every function that
+include/dcp.h declares, sizes workspaces, and rejects bad arguments before
+enqueuing anything.  No GPU needed: every call below fails validation, so
+no HIP call is made (the device pointers are never dereferenced)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2107_00555_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2107_00555_amd import build
+        build.build(verbose=False)
+    return _lib
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "dcp.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(dcp_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_four_entry_points():
+    names = header_functions()
+    for n in ("dcp_step_fused", "dcp_step_unfused", "dcp_run", "dcp_adjoint_run",
+              "dcp_workspace_bytes", "dcp_status_string"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    lib = L.lib()
+    for n in header_functions():
+        assert hasattr(lib, n), n
+        assert ctypes.cast(getattr(lib, n), ctypes.c_void_p).value
+
+
+def test_status_strings(L):
+    lib = L.lib()
+    for s in (0, -1, -2, -3, -4, -5, -6, -7, -100):
+        assert lib.dcp_status_string(s)
+    assert lib.dcp_status_string(12345) == b"unknown status"
+
+
+def test_workspace_sizes(L):
+    GiB = 1 << 30
+    w = L.workspace_bytes(L.OP_RUN, L.F64, 512, 512, 512, T=100, norms=True)
+    assert GiB <= w < GiB + (64 << 20)            # one field plus small partials
+    w = L.workspace_bytes(L.OP_RUN, L.F64, 512, 512, 512, T=100, norms=False, impl=L.UNFUSED)
+    assert w == 4 * GiB                            # ping-pong field + 3 temporaries
+    w = L.workspace_bytes(L.OP_RUN, L.F32, 512, 512, 512, T=100, norms=False)
+    assert w == GiB // 2
+    assert L.workspace_bytes(L.OP_STEP_FUSED, L.F64, 64, 64, 64) == 0
+    w = L.workspace_bytes(L.OP_ADJOINT, L.F64, 256, 256, 256, T=50, ckpt_every=10)
+    assert 11 * 128 * (1 << 20) <= w < 11 * 128 * (1 << 20) + (16 << 20)  # 2 lambdas + 9 states
+    assert L.workspace_bytes(L.OP_RUN, L.F64, 0, 5, 5, T=3, norms=True) == 0
+    assert L.workspace_bytes(L.OP_RUN, L.F64, 4, 4, 4, T=0, norms=True) == 0
+
+
+@pytest.mark.parametrize("args,code", [
+    (dict(op=9), -5), (dict(dtype=7), -3), (dict(nx=-1), -2), (dict(T=-1), -5),
+    (dict(op=3, ckpt_every=0), -5), (dict(tblock=0), -5), (dict(impl=5), -5),
+    (dict(nx=1 << 40), -2),
+])
+def test_workspace_bytes_errors(L, args, code):
+    a = dict(op=L.OP_RUN, dtype=L.F64, impl=L.FUSED, nx=8, ny=8, nz=8, T=4, ckpt_every=2,
+             tblock=1, norms=1)
+    a.update(args)
+    out = ctypes.c_size_t(0)
+    rc = L.lib().dcp_workspace_bytes(a["op"], a["dtype"], a["impl"], a["nx"], a["ny"], a["nz"],
+                                     a["T"], a["ckpt_every"], a["tblock"], a["norms"],
+                                     ctypes.byref(out))
+    assert rc == code
+    assert L.lib().dcp_workspace_bytes(0, 0, 0, 4, 4, 4, 1, 1, 1, 0, None) == -1
+
+
+# Fake, never-dereferenced device addresses, far apart (no overlap).
+U, F, O, WS = 0x10000000, 0x20000000, 0x30000000, 0x40000000
+C = None
+
+
+def coeffs(L, **kw):
+    d = dict(alpha=1.0, beta=0.1, gamma=0.5, h=1.0, dt=0.1)
+    d.update(kw)
+    return L.Coeffs.make(d)
+
+
+def step_call(L, fn="dcp_step_fused", dtype=0, u=U, f=F, o=O, n=(8, 8, 8), c=None, bc=0,
+              norms=None, ws=WS, wsb=1 << 26):
+    c = coeffs(L) if c is None else c
+    return getattr(L.lib(), fn)(dtype, u, f, o, n[0], n[1], n[2], ctypes.byref(c), bc, norms, ws,
+                                wsb, None)
+
+
+@pytest.mark.parametrize("fn", ["dcp_step_fused", "dcp_step_unfused"])
+def test_step_argument_errors(L, fn):
+    assert step_call(L, fn, dtype=2) == -3
+    assert step_call(L, fn, n=(-1, 8, 8)) == -2
+    assert step_call(L, fn, bc=3) == -4
+    assert step_call(L, fn, u=None) == -1
+    assert step_call(L, fn, o=None) == -1
+    assert step_call(L, fn, c=coeffs(L, h=0.0)) == -5
+    assert step_call(L, fn, c=coeffs(L, alpha=float("nan"))) == -5
+    assert step_call(L, fn, c=coeffs(L, dt=float("inf"))) == -5
+    assert step_call(L, fn, o=U) == -7                       # u_out aliases u
+    assert step_call(L, fn, o=F + 8) == -7                   # u_out overlaps f
+    lib = L.lib()
+    assert getattr(lib, fn)(0, U, F, O, 8, 8, 8, None, 0, None, None, 0, None) == -1  # no coeffs
+    # norms requested without a workspace
+    assert step_call(L, fn, norms=0x50000000, ws=None, wsb=0) == -6
+    assert step_call(L, fn, norms=0x50000000, ws=None, wsb=1 << 30) == -1
+    # workspace overlapping an input
+    if fn == "dcp_step_unfused":
+        assert step_call(L, fn, ws=None, wsb=0) == -6        # unfused always needs temporaries
+        assert step_call(L, fn, ws=U, wsb=1 << 20) == -7
+
+
+def run_call(L, dtype=0, impl=0, u=U, f=F, n=(8, 8, 8), c=None, bc=1, T=4, tblock=1, energy=None,
+             resid=None, ckpt=None, k=0, ws=WS, wsb=1 << 24):
+    c = coeffs(L) if c is None else c
+    return L.lib().dcp_run(dtype, impl, u, f, n[0], n[1], n[2], ctypes.byref(c), bc, T, tblock,
+                           energy, resid, ckpt, k, ws, wsb, None)
+
+
+def test_run_argument_errors(L):
+    assert run_call(L, T=-1) == -5
+    assert run_call(L, impl=2) == -5
+    assert run_call(L, tblock=0) == -5
+    assert run_call(L, tblock=L.lib().dcp_max_tblock(0) + 1) == -5
+    assert run_call(L, ckpt=0x50000000, k=0) == -5
+    assert run_call(L, f=U) == -7                                 # f aliases u
+    assert run_call(L, ckpt=U + 64, k=2) == -7                    # checkpoints overlap u
+    assert run_call(L, ws=F) == -7                                # workspace overlaps f
+    assert run_call(L, wsb=16) == -6
+    assert run_call(L, u=None) == -1
+    assert run_call(L, energy=0x50000000, resid=0x50000008) == -7  # norm outputs overlap
+    assert run_call(L, bc=-1) == -4
+    assert run_call(L, dtype=-1) == -3
+
+
+def adj_call(L, dtype=0, ckpt=0x50000000, k=2, f=F, lam=U, n=(8, 8, 8), c=None, bc=0, T=4, g=O,
+             gab=0x60000000, ws=WS, wsb=1 << 26):
+    c = coeffs(L) if c is None else c
+    return L.lib().dcp_adjoint_run(dtype, ckpt, k, f, lam, n[0], n[1], n[2], ctypes.byref(c), bc,
+                                   T, g, gab, ws, wsb, None)
+
+
+def test_adjoint_argument_errors(L):
+    assert adj_call(L, k=0) == -5
+    assert adj_call(L, T=-2) == -5
+    assert adj_call(L, gab=None) == -1
+    assert adj_call(L, ckpt=None) == -1
+    assert adj_call(L, g=U) == -7          # grad_u0 aliases lam_T
+    assert adj_call(L, g=0x50000000) == -7  # grad_u0 overlaps the checkpoints
+    assert adj_call(L, wsb=8) == -6
+    assert adj_call(L, ws=F) == -7
+    assert adj_call(L, c=coeffs(L, beta=float("-inf"))) == -5

@@ -1,0 +1,194 @@
+"""Forward parity: the HIP path against the CPU oracle, element by element,
+on seeded inputs.  Shapes span several tiles along every axis and end in
+ragged tails (tiles are 128 or 256 points along x, 8-16 rows along y and
+8-64 planes along z), plus the degenerate grids.
+
+Tolerances: float64 1e-12 normwise, float32 1e-5 normwise against the FP64
+oracle run on the float32-rounded inputs; the unfused float64 chain rounds
+every statement exactly as the oracle does and must match it bit for bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import (BASE, DEV, f32_round, misaligned_like, normwise, rand_fields, say,
+                      to_dev, to_host)
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(64, 64, 64), (67, 33, 17), (200, 40, 33), (130, 5, 3), (1, 1, 9), (1, 1, 1),
+          (2, 3, 4), (3, 70, 2), (256, 17, 70), (513, 9, 5)]
+BCS = [0, 1]
+
+
+def _api():
+    from paper_2107_00555_amd import api
+    return api
+
+
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("shape", SHAPES)
+def test_fused_f64_matches_oracle(shape, bc):
+    api = _api()
+    u0, f = rand_fields(shape, 100 + sum(shape))
+    T = 6
+    want, e_want, r_want = oracle.run(u0, f, BASE, T, bc)
+    say("fused f64", shape, bc)
+    u = to_dev(u0)
+    out = api.run(u, to_dev(f), BASE, T, bc, impl="fused", norms=True)
+    torch.cuda.synchronize()
+    assert normwise(to_host(u), want) <= 1e-12
+    np.testing.assert_allclose(to_host(out["energy"]), e_want, rtol=1e-12)
+    np.testing.assert_allclose(to_host(out["resid"]), r_want, rtol=1e-11)
+
+
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("shape", SHAPES)
+def test_unfused_f64_is_bitwise_oracle(shape, bc):
+    api = _api()
+    u0, f = rand_fields(shape, 200 + sum(shape))
+    T = 4
+    want, e_want, r_want = oracle.run(u0, f, BASE, T, bc)
+    say("unfused f64", shape, bc)
+    u = to_dev(u0)
+    out = api.run(u, to_dev(f), BASE, T, bc, impl="unfused", norms=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(u), want)
+    np.testing.assert_allclose(to_host(out["energy"]), e_want, rtol=1e-12)
+    np.testing.assert_allclose(to_host(out["resid"]), r_want, rtol=1e-11)
+
+
+@pytest.mark.parametrize("impl", ["fused", "unfused"])
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("shape", [(64, 64, 64), (67, 33, 17), (256, 17, 70), (1, 1, 9), (5, 3, 2)])
+def test_f32_matches_oracle(shape, bc, impl):
+    api = _api()
+    u0, f = rand_fields(shape, 300 + sum(shape))
+    u0, f = f32_round(u0), f32_round(f)
+    T = 10
+    want, e_want, r_want = oracle.run(u0, f, BASE, T, bc)
+    say("f32", impl, shape, bc)
+    u = to_dev(u0, torch.float32)
+    out = api.run(u, to_dev(f, torch.float32), BASE, T, bc, impl=impl, norms=True)
+    torch.cuda.synchronize()
+    assert normwise(to_host(u), want) <= 1e-5
+    np.testing.assert_allclose(to_host(out["energy"]), e_want, rtol=1e-5)
+    np.testing.assert_allclose(to_host(out["resid"]), r_want, rtol=1e-4)
+
+
+@pytest.mark.parametrize("impl", ["fused", "unfused"])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_single_step_and_norms(impl, dtype):
+    api = _api()
+    shape, bc = (70, 20, 12), 1
+    u0, f = rand_fields(shape, 7)
+    if dtype == torch.float32:
+        u0, f = f32_round(u0), f32_round(f)
+    want, e_want, r_want = oracle.run(u0, f, BASE, 1, bc)
+    say("single step", impl, dtype)
+    out, n2 = api.step(to_dev(u0, dtype), to_dev(f, dtype), BASE, bc, impl=impl, norms=True)
+    torch.cuda.synchronize()
+    tol = 1e-12 if dtype == torch.float64 else 1e-5
+    assert normwise(to_host(out), want) <= (0 if (impl == "unfused" and dtype == torch.float64) else tol)
+    n2 = to_host(n2)
+    assert n2[0] == pytest.approx(e_want[0], rel=tol)
+    assert n2[1] == pytest.approx(r_want[0] ** 2, rel=10 * tol)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("bc", BCS)
+def test_run_equals_repeated_steps_and_checkpoints(dtype, bc):
+    api = _api()
+    shape, T, k = (130, 36, 20), 7, 3
+    u0, f = rand_fields(shape, 11)
+    fd = to_dev(f, dtype)
+    say("run vs steps", dtype, bc)
+    states = [to_dev(u0, dtype)]
+    for _ in range(T):
+        nxt, _ = api.step(states[-1], fd, BASE, bc, impl="fused")
+        states.append(nxt)
+    u_plain = to_dev(u0, dtype)
+    api.run(u_plain, fd, BASE, T, bc, norms=False)
+    u_ck = to_dev(u0, dtype)
+    out = api.run(u_ck, fd, BASE, T, bc, norms=True, ckpt_every=k)
+    torch.cuda.synchronize()
+    assert torch.equal(u_plain, states[-1])
+    assert torch.equal(u_ck, states[-1])
+    ck = out["ckpt"]
+    assert ck.shape[0] == 3
+    for c in range(ck.shape[0]):
+        assert torch.equal(ck[c], states[c * k])
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_run_is_bitwise_reproducible(dtype):
+    api = _api()
+    shape, T = (96, 48, 40), 5
+    u0, f = rand_fields(shape, 12)
+    say("reproducible", dtype)
+    res = []
+    for _ in range(3):
+        u = to_dev(u0, dtype)
+        out = api.run(u, to_dev(f, dtype), BASE, T, 1, norms=True)
+        res.append((u, out["energy"], out["resid"]))
+    torch.cuda.synchronize()
+    for u, e, r in res[1:]:
+        assert torch.equal(u, res[0][0]) and torch.equal(e, res[0][1]) and torch.equal(r, res[0][2])
+
+
+@pytest.mark.parametrize("impl", ["fused", "unfused"])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_unaligned_pointers_take_the_scalar_path_with_same_result(impl, dtype):
+    api = _api()
+    shape, bc = (64, 24, 20), 0
+    u0, f = rand_fields(shape, 13)
+    say("unaligned", impl, dtype)
+    ua, fa = to_dev(u0, dtype), to_dev(f, dtype)
+    oa, na = api.step(ua, fa, BASE, bc, impl=impl, norms=True)
+    um, fm = misaligned_like(ua), misaligned_like(fa)
+    om, nm = api.step(um, fm, BASE, bc, impl=impl, norms=True)
+    torch.cuda.synchronize()
+    assert torch.equal(oa, om)
+    assert torch.allclose(na, nm, rtol=1e-13, atol=0)
+
+
+def test_zero_steps_and_empty_grids():
+    api = _api()
+    u0, f = rand_fields((9, 8, 7), 14)
+    u = to_dev(u0)
+    out = api.run(u, to_dev(f), BASE, 0, 1, norms=True)
+    assert out["energy"].numel() == 0
+    assert np.array_equal(to_host(u), u0)
+    say("empty grid")
+    e = torch.empty((0, 4, 4), dtype=torch.float64, device=DEV)
+    out = api.run(e, torch.empty_like(e), BASE, 3, 0, norms=True)
+    _, n2 = api.step(e, torch.empty_like(e), BASE, 0, norms=True)
+    torch.cuda.synchronize()
+    assert torch.equal(out["energy"], torch.zeros(3, dtype=torch.float64, device=DEV))
+    assert torch.equal(out["resid"], torch.zeros(3, dtype=torch.float64, device=DEV))
+    assert torch.equal(n2, torch.zeros(2, dtype=torch.float64, device=DEV))
+
+
+def test_nan_propagates_to_norms():
+    api = _api()
+    u0, f = rand_fields((40, 30, 20), 15)
+    u0[3, 4, 5] = np.nan
+    out = api.run(to_dev(u0), to_dev(f), BASE, 3, 1, norms=True)
+    torch.cuda.synchronize()
+    assert torch.isnan(out["energy"]).all() and torch.isnan(out["resid"]).all()
+
+
+def test_python_binding_rejects_bad_tensors():
+    api = _api()
+    u = torch.zeros((4, 4, 4), dtype=torch.float64, device=DEV)
+    with pytest.raises(TypeError):
+        api.step(u.to(torch.int32), u.to(torch.int32), BASE, 0)
+    with pytest.raises(ValueError):
+        api.step(u, torch.zeros((4, 4, 5), dtype=torch.float64, device=DEV), BASE, 0)
+    with pytest.raises(ValueError):
+        api.step(u.transpose(0, 2), u, BASE, 0)
+    with pytest.raises(ValueError):
+        api.step(u.cpu(), u.cpu(), BASE, 0)
+    with pytest.raises(api.DcpError):
+        api.run(u, u.clone(), BASE, 3, 0, tblock=1000)
