@@ -1,0 +1,301 @@
+#!/usr/bin/env python3
+"""Benchmark of the fused reaction-diffusion program on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--seed S] [--forms main|all]
+                    [--no-cpu-baseline] [--calibrate-copy]
+
+Workload (the headline configuration): a 512^3 float64 grid, periodic
+boundary, u0 ~ U[-1,1], f = 8 seeded low-frequency sinusoids, alpha=1,
+beta=0.1, gamma=0.5, h=1, dt=0.1.  One timed step is one dcp_run of T=100
+fused time steps with the FP64 energy and residual norms of every step
+(inputs resident in HBM; each step continues from the state the previous
+one left).  W untimed steps, then exactly K timed steps between two device
+synchronisations.  `value` is lattice-point updates per second (GLUP/s =
+N*T*K / seconds / 1e9).
+
+In the same run (--forms all, the default) every other form of the metric
+is timed on the same inputs, each in its own event-timed region: the
+unfused single-operator chain, the float32 forms, the adjoint kernel and
+the end-to-end gradient (forward with checkpoints + checkpointed adjoint).
+
+Prints ONE JSON line.  With --gpus N, N > 1, it exits with a message: this
+benchmark runs on one GPU only.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+KERNEL_SRC = os.path.join(ROOT, "paper_2107_00555_amd", "csrc", "dcp_kernels.hip")
+COUNTERS = os.path.join(ROOT, "profiles", "stencil_fused_f64_512_counters.md")
+
+
+def parse():
+    p = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--seed", type=int, default=0)
+    p.add_argument("--forms", choices=["main", "all"], default="all")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--calibrate-copy", action="store_true",
+                   help="also run a plain 1 GiB device copy (counter calibration)")
+    p.add_argument("--tblock", type=int, default=1)
+    return p.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def bootstrap_ci(xs, reps=2000, seed=0):
+    """Median and 95% nonparametric bootstrap interval of the median."""
+    import numpy as np
+    xs = np.asarray(xs, dtype=np.float64)
+    if xs.size == 0:
+        return None, None, None
+    r = np.random.default_rng(seed)
+    meds = np.median(r.choice(xs, size=(reps, xs.size), replace=True), axis=1)
+    return float(np.median(xs)), float(np.percentile(meds, 2.5)), float(np.percentile(meds, 97.5))
+
+
+def timed(fn, k, w, stream):
+    """W untimed calls, then K calls with an event between each; returns
+    (total_ms by events, per-call ms list, wall seconds)."""
+    import torch
+    for _ in range(w):
+        fn()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(k + 1)]
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for i in range(k):
+        fn()
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = [ev[i].elapsed_time(ev[i + 1]) for i in range(k)]
+    return ev[0].elapsed_time(ev[k]), per, wall
+
+
+def counter_traffic():
+    """HBM bytes per launch of the fused FP64 kernel from the committed
+    rocprofv3 counter summary, or None if the kernel source changed since."""
+    if not os.path.exists(COUNTERS):
+        return None
+    src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    vals = {}
+    for line in open(COUNTERS):
+        if ":" in line and line.strip().startswith("- "):
+            k, v = line.strip()[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256") != src:
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(u0, f, coeffs, bc):
+    """The oracle as it stands, serial, on 2 of the 100 steps of the same
+    512^3 workload (full grid)."""
+    import oracle
+    T = 2
+    t0 = time.perf_counter()
+    oracle.run(u0, f, coeffs, T, bc, norms=True)
+    dt = time.perf_counter() - t0
+    n = u0.size
+    return {"value": n * T / dt / 1e9, "unit": "GLUP/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle_run (serial FP64, every temporary materialised) for 2 of the 100 "
+                      f"steps on the full 512^3 periodic grid, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only (the single-GPU kernels are the measured path); "
+              "multi-GPU runs are not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2107_00555_amd import _lib, api, inputs
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    nx = ny = nz = 512
+    N = nx * ny * nz
+    T = 100
+    bc = inputs.PERIODIC
+    coeffs = dict(inputs.BASE_COEFFS)
+
+    log("generating inputs 512^3 ...")
+    t0 = time.perf_counter()
+    u0_h, f_h = inputs.make_fields("fwd_512_f64", seed=args.seed)
+    log(f"  inputs ready in {time.perf_counter() - t0:.1f} s")
+    u0 = torch.from_numpy(u0_h).to(dev)
+    f64 = torch.from_numpy(f_h).to(dev)
+    u = u0.clone()
+
+    # ---------------------------------------------------------- headline
+    ws = api.workspace(_lib.workspace_bytes(_lib.OP_RUN, _lib.F64, nx, ny, nz, T=T, norms=True,
+                                            tblock=args.tblock), dev)
+    res = {}
+
+    def fused_step():
+        res["out"] = api.run(u, f64, coeffs, T, bc, impl="fused", tblock=args.tblock, norms=True, ws=ws)
+
+    if args.calibrate_copy:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).uniform_()
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)  # plain 1 GiB read + 1 GiB write
+        torch.cuda.synchronize()
+        del src, dst
+
+    log(f"timing fused f64: T={T}, K={args.steps}, W={args.warmup}")
+    total_ms, per, wall = timed(fused_step, args.steps, args.warmup, stream)
+    ms_step = total_ms / args.steps
+    value = N * T * args.steps / (total_ms / 1e3) / 1e9
+    launch_ms = total_ms / (args.steps * T)        # average fused-kernel launch (upper bound)
+    bytes_per_launch = 3 * 8 * N                    # read u, read f, write u' (algorithmic)
+    achieved = bytes_per_launch / (launch_ms / 1e3) / 1e9
+    med, lo, hi = bootstrap_ci(per)
+    e = res["out"]["energy"]
+    if not torch.isfinite(e).all():
+        raise RuntimeError("non-finite norms in the timed run")
+    traffic = counter_traffic()
+
+    out = {
+        "metric": "GLUP/s and % HBM roofline, fused vs unfused, fwd+adjoint, FP64/FP32 at 512^3",
+        "value": round(value, 3),
+        "unit": "GLUP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded: u0 ~ U[-1,1], f = 8 low-frequency sinusoids)",
+        "config": {"workload": "fwd_512_f64: 512^3 float64, periodic, fused forward, T=100 steps "
+                               "per step of the benchmark, FP64 energy+residual norms every step",
+                   "grid": [nx, ny, nz], "T": T, "bc": "periodic", "impl": "fused",
+                   "tblock": args.tblock, "coeffs": coeffs, "parallelism": "single-gpu"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "kernel": "stencil_kernel<double,2,1,4,4,PERIODIC,FWD,norms>",
+                     "bytes_per_launch": bytes_per_launch,
+                     "avg_launch_ms": round(launch_ms, 5)},
+        "stats": {"median_ms": med, "ci95_ms": [lo, hi], "wall_s": round(wall, 4)},
+    }
+
+    # ------------------------------------------------------- other forms
+    if args.forms == "all":
+        forms = {}
+        out["forms"] = forms
+        kk = max(1, min(args.steps, 3))
+
+        def glups(ms, steps=T):
+            return N * steps / (ms / 1e3) / 1e9
+
+        def frac(ms, bpl, steps=T):
+            return (bpl * N * steps / (ms / 1e3) / 1e9) / HBM_PEAK_GBS
+
+        forms["fused_f64"] = {"glups": round(value, 3), "ms": round(ms_step, 3),
+                              "hbm_frac": round(frac(ms_step, 24), 4)}
+
+        # unfused chain, float64
+        wsu = api.workspace(_lib.workspace_bytes(_lib.OP_RUN, _lib.F64, nx, ny, nz, T=T, norms=True,
+                                                 impl=_lib.UNFUSED), dev)
+        uu = u0.clone()
+        log("timing unfused f64")
+        ms_u, per_u, _ = timed(lambda: api.run(uu, f64, coeffs, T, bc, impl="unfused", norms=True, ws=wsu),
+                               kk, 1, stream)
+        ms_u /= kk
+        forms["unfused_f64"] = {"glups": round(glups(ms_u), 3), "ms": round(ms_u, 3),
+                                "bytes_per_lup": 21 * 8 + 16,
+                                "hbm_frac": round(frac(ms_u, 21 * 8 + 16), 4)}
+        forms["fused_speedup_over_unfused_f64"] = round(ms_u / ms_step, 3)
+        del wsu, uu
+
+        # float32 forms
+        u32 = u0.to(torch.float32)
+        f32 = f64.to(torch.float32)
+        ws32 = api.workspace(_lib.workspace_bytes(_lib.OP_RUN, _lib.F32, nx, ny, nz, T=T, norms=True,
+                                                  impl=_lib.UNFUSED), dev)
+        log("timing fused f32")
+        ms_f32, _, _ = timed(lambda: api.run(u32, f32, coeffs, T, bc, impl="fused", norms=True, ws=ws32),
+                             args.steps, 1, stream)
+        ms_f32 /= args.steps
+        forms["fused_f32"] = {"glups": round(glups(ms_f32), 3), "ms": round(ms_f32, 3),
+                              "hbm_frac": round(frac(ms_f32, 12), 4)}
+        u32b = u0.to(torch.float32)
+        log("timing unfused f32")
+        ms_u32, _, _ = timed(lambda: api.run(u32b, f32, coeffs, T, bc, impl="unfused", norms=True, ws=ws32),
+                             kk, 1, stream)
+        ms_u32 /= kk
+        forms["unfused_f32"] = {"glups": round(glups(ms_u32), 3), "ms": round(ms_u32, 3),
+                                "hbm_frac": round(frac(ms_u32, 21 * 4 + 8), 4)}
+        forms["fused_speedup_over_unfused_f32"] = round(ms_u32 / ms_f32, 3)
+        del ws32, u32b
+
+        # adjoint kernel alone: k = 1 (no recomputation), 10 steps
+        for name, dtype, fld, ff in (("f64", torch.float64, u0, f64), ("f32", torch.float32, u32, f32)):
+            S = 8 if dtype == torch.float64 else 4
+            Ta = 10
+            ua = fld.clone().to(dtype)
+            ck = api.run(ua, ff, coeffs, Ta, bc, norms=False, ckpt_every=1)["ckpt"]
+            lam = (ua - fld.to(dtype)).contiguous()
+            wsa = api.workspace(_lib.workspace_bytes(_lib.OP_ADJOINT, 0 if S == 8 else 1, nx, ny, nz,
+                                                     T=Ta, ckpt_every=1), dev)
+            g = torch.empty_like(lam)
+            log(f"timing adjoint kernel {name}")
+            ms_a, _, _ = timed(lambda: api.adjoint_run(ck, 1, ff, lam, coeffs, Ta, bc, ws=wsa, grad_u0=g),
+                               kk, 1, stream)
+            ms_a /= kk
+            forms[f"adjoint_{name}"] = {"glups": round(glups(ms_a, Ta), 3), "ms_per_step": round(ms_a / Ta, 4),
+                                        "hbm_frac": round(frac(ms_a, 3 * S, Ta), 4)}
+            del ck, wsa, g, lam, ua
+
+        # end-to-end gradient, float64: forward T=100 with checkpoints every 10, then adjoint
+        kck = 10
+        ug = u0.clone()
+        ck = torch.empty((T // kck, nz, ny, nx), dtype=torch.float64, device=dev)
+        wsf = api.workspace(_lib.workspace_bytes(_lib.OP_RUN, _lib.F64, nx, ny, nz, T=T), dev)
+        wsa = api.workspace(_lib.workspace_bytes(_lib.OP_ADJOINT, _lib.F64, nx, ny, nz, T=T, ckpt_every=kck), dev)
+        g = torch.empty_like(u0)
+
+        def grad_step():
+            ug.copy_(u0)
+            api.run(ug, f64, coeffs, T, bc, norms=False, ckpt_every=kck, ws=wsf, ckpt=ck)
+            api.adjoint_run(ck, kck, f64, ug, coeffs, T, bc, ws=wsa, grad_u0=g)
+
+        log("timing end-to-end gradient f64")
+        ms_g, _, _ = timed(grad_step, kk, 1, stream)
+        ms_g /= kk
+        forms["gradient_f64_T100_k10"] = {"ms": round(ms_g, 3),
+                                          "ms_over_forward": round(ms_g / ms_step, 3)}
+        del ck, wsf, wsa, g, ug, u32, f32
+
+    # --------------------------------------------------------- CPU oracle
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle (bounded sample) ...")
+        out["cpu_baseline"] = cpu_baseline(u0_h, f_h, coeffs, bc)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
