@@ -157,11 +157,12 @@ def main():
         res["out"] = api.run(u, f64, coeffs, T, bc, impl="fused", tblock=args.tblock, norms=True, ws=ws)
 
     if args.calibrate_copy:
-        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).uniform_()
-        dst = torch.empty_like(src)
-        torch.mul(src, 1.0, out=dst)  # plain 1 GiB read + 1 GiB write
+        # the library's own copy kernel, 1 GiB read + 1 GiB write: a dcp_run of
+        # one step with a checkpoint every step copies u into slot 0 first
+        uc = u0.clone()
+        api.run(uc, f64, coeffs, 1, bc, norms=False, ckpt_every=1)
         torch.cuda.synchronize()
-        del src, dst
+        del uc
 
     log(f"timing fused f64: T={T}, K={args.steps}, W={args.warmup}")
     total_ms, per, wall = timed(fused_step, args.steps, args.warmup, stream)

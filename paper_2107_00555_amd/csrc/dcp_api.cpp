@@ -445,7 +445,7 @@ int dcp_run(int dtype, int impl, void *u, const void *f, int64_t nx, int64_t ny,
     const int nblk_red = impl == DCP_UNFUSED ? ew_norm_blocks(g.n) : t.nblk;
     double *partials = norms ? reinterpret_cast<double *>(at(ws, w.partials)) : nullptr;
 
-    if (nslots > 0) DCP_TRY(hipMemcpyAsync(slot(0), u, fb, hipMemcpyDeviceToDevice, st));
+    if (nslots > 0) DCP_TRY(launch_ew(dtype, EW_COPY, u, nullptr, slot(0), 0.0, g.n, vok, st));
     const void *cur = u;
     for (int32_t s = 0; s < T; ++s) {
         void *nxt;
@@ -461,7 +461,7 @@ int dcp_run(int dtype, int impl, void *u, const void *f, int64_t nx, int64_t ny,
             DCP_TRY(unfused_step(dtype, bc, g, *coeffs, t, vok, cur, f, nxt, tmp, p, st));
         cur = nxt;
     }
-    if (cur != u) DCP_TRY(hipMemcpyAsync(u, cur, fb, hipMemcpyDeviceToDevice, st));
+    if (cur != u) DCP_TRY(launch_ew(dtype, EW_COPY, cur, nullptr, u, 0.0, g.n, vok, st));
     if (norms) DCP_TRY(launch_finalize(partials, nblk_red, T, energy, resid, 1, st));
     return DCP_OK;
 }
@@ -493,7 +493,9 @@ int dcp_adjoint_run(int dtype, const void *ckpt, int32_t ckpt_every, const void 
 
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (T == 0 || g.n == 0) {
-        if (g.n > 0) DCP_TRY(hipMemcpyAsync(grad_u0, lam_T, fb, hipMemcpyDeviceToDevice, st));
+        if (g.n > 0)
+            DCP_TRY(launch_ew(dtype, EW_COPY, lam_T, nullptr, grad_u0, 0.0, g.n,
+                              vec_ok_for(dtype, g, {lam_T, grad_u0}), st));
         DCP_TRY(launch_zero(grad_ab, 2, st));
         return DCP_OK;
     }

@@ -46,8 +46,9 @@ Shape shape_at(int i);
 hipError_t launch_stencil(int dtype, int op, int bc, bool reduce, const Tile &t,
                           const StencilArgs &a, hipStream_t stream);
 
-// Element-wise statements of the unfused program.
-enum EwOp : int { EW_POW3 = 0, EW_SCALE = 1, EW_SUB = 2, EW_ADD = 3 };
+// Element-wise statements of the unfused program, and a plain copy (o = x)
+// used for checkpoint slots and copy-backs.
+enum EwOp : int { EW_POW3 = 0, EW_SCALE = 1, EW_SUB = 2, EW_ADD = 3, EW_COPY = 4 };
 hipError_t launch_ew(int dtype, int op, const void *x, const void *y, void *o,
                      double a, int64_t n, bool vec_ok, hipStream_t stream);
 

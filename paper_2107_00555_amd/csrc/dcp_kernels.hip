@@ -360,7 +360,8 @@ __device__ __forceinline__ void ew_apply(T (&o)[VEC], const T (&x)[VEC], const T
         if constexpr (OPC == EW_POW3) o[i] = (x[i] * x[i]) * x[i];
         else if constexpr (OPC == EW_SCALE) o[i] = a * x[i];
         else if constexpr (OPC == EW_SUB) o[i] = x[i] - y[i];
-        else o[i] = x[i] + y[i];
+        else if constexpr (OPC == EW_ADD) o[i] = x[i] + y[i];
+        else o[i] = x[i];
     }
 }
 
@@ -521,14 +522,16 @@ hipError_t launch_ew_t(int op, const void *x, const void *y, void *o, double a, 
             case EW_POW3: DCP_EW(W, EW_POW3); break;
             case EW_SCALE: DCP_EW(W, EW_SCALE); break;
             case EW_SUB: DCP_EW(W, EW_SUB); break;
-            default: DCP_EW(W, EW_ADD); break;
+            case EW_ADD: DCP_EW(W, EW_ADD); break;
+            default: DCP_EW(W, EW_COPY); break;
         }
     } else {
         switch (op) {
             case EW_POW3: DCP_EW(1, EW_POW3); break;
             case EW_SCALE: DCP_EW(1, EW_SCALE); break;
             case EW_SUB: DCP_EW(1, EW_SUB); break;
-            default: DCP_EW(1, EW_ADD); break;
+            case EW_ADD: DCP_EW(1, EW_ADD); break;
+            default: DCP_EW(1, EW_COPY); break;
         }
     }
 #undef DCP_EW

@@ -51,35 +51,38 @@ def sinusoid_params(seed: int, stream: int = STREAM_F, count: int = 8):
 
 
 def sinusoids(nx: int, ny: int, nz: int, seed: int, stream: int = STREAM_F,
-              count: int = 8, out: np.ndarray | None = None,
-              zchunk: int = 32) -> np.ndarray:
+              count: int = 8, box=None) -> np.ndarray:
     """f = sum_j a_j sin(2 pi (mx x/nx + my y/ny + mz z/nz) + phi_j).
 
-    Periodic on the grid and smooth.  Evaluated as
-    sin(A + B) = sin A cos B + cos A sin B with A over (y, x) and B over z,
-    in z-chunks, so the 512^3 and 1024x1024x512 grids stay cheap to build.
+    Periodic on the grid and smooth.  ``box`` = ((x0, x1), (y0, y1), (z0, z1))
+    evaluates the same field on a sub-box of the (nx, ny, nz) grid only.
+    With sin(A + B) = sin A cos B + cos A sin B, A over (y, x) and B over z,
+    the sum over modes is one product of a (z, 2*count) by a (2*count, y*x)
+    matrix, which keeps the 512^3 and 1024x1024x512 grids cheap to build.
     """
     modes = sinusoid_params(seed, stream, count)
-    if out is None:
-        out = np.zeros((nz, ny, nx), dtype=np.float64)
-    else:
-        out[...] = 0.0
-    x = np.arange(nx, dtype=np.float64)
-    y = np.arange(ny, dtype=np.float64)
-    z = np.arange(nz, dtype=np.float64)
-    for mx, my, mz, a, phi in modes:
+    (x0, x1), (y0, y1), (z0, z1) = box if box is not None else ((0, nx), (0, ny), (0, nz))
+    x = np.arange(x0, x1, dtype=np.float64)
+    y = np.arange(y0, y1, dtype=np.float64)
+    z = np.arange(z0, z1, dtype=np.float64)
+    k = len(modes)
+    S = np.empty((2 * k, y.size * x.size))
+    W = np.empty((z.size, 2 * k))
+    for j, (mx, my, mz, a, phi) in enumerate(modes):
         A = (2.0 * np.pi * (my * y / ny))[:, None] + (2.0 * np.pi * (mx * x / nx))[None, :] + phi
-        sA = a * np.sin(A)
-        cA = a * np.cos(A)
+        S[j] = (a * np.sin(A)).ravel()
+        S[k + j] = (a * np.cos(A)).ravel()
         B = 2.0 * np.pi * (mz * z / nz)
-        sB = np.sin(B)
-        cB = np.cos(B)
-        for z0 in range(0, nz, zchunk):
-            z1 = min(nz, z0 + zchunk)
-            blk = out[z0:z1]
-            blk += sA[None, :, :] * cB[z0:z1, None, None]
-            blk += cA[None, :, :] * sB[z0:z1, None, None]
-    return out
+        W[:, j] = np.cos(B)
+        W[:, k + j] = np.sin(B)
+    return (W @ S).reshape(z.size, y.size, x.size)
+
+
+def uniform_zslab(nx: int, ny: int, nz_lo: int, seed: int, stream: int) -> np.ndarray:
+    """The first nz_lo z-planes of uniform(nx, ny, nz, seed, stream) for any
+    nz >= nz_lo (the generator fills the array in C order, so a shorter draw
+    is a prefix of a longer one)."""
+    return rng(seed, stream).uniform(-1.0, 1.0, size=(nz_lo, ny, nx))
 
 
 def fd_directions(nx: int, ny: int, nz: int, seed: int, count: int):

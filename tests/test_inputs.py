@@ -18,7 +18,7 @@ def test_uniform_is_deterministic_and_streams_differ():
 
 def test_sinusoids_match_direct_definition_and_are_periodic():
     nx, ny, nz = 16, 12, 10
-    f = inputs.sinusoids(nx, ny, nz, seed=3, zchunk=3)
+    f = inputs.sinusoids(nx, ny, nz, seed=3)
     modes = inputs.sinusoid_params(seed=3)
     assert len(modes) == 8
     for mx, my, mz, a, phi in modes:
@@ -42,3 +42,12 @@ def test_fd_directions_deterministic():
     for (a, b, c), (x, y, z) in zip(d1, d2):
         assert np.array_equal(a, x) and b == y and c == z
     assert not np.array_equal(d1[0][0], d1[1][0])
+
+
+def test_sinusoid_box_and_zslab_are_crops_of_the_full_fields():
+    nx, ny, nz = 12, 10, 8
+    full = inputs.sinusoids(nx, ny, nz, seed=4)
+    box = inputs.sinusoids(nx, ny, nz, seed=4, box=((2, 9), (0, 4), (3, 8)))
+    assert np.max(np.abs(box - full[3:8, 0:4, 2:9])) < 1e-13
+    u = inputs.uniform(nx, ny, nz, seed=4, stream=inputs.STREAM_U0)
+    assert np.array_equal(inputs.uniform_zslab(nx, ny, 3, seed=4, stream=inputs.STREAM_U0), u[:3])
