@@ -103,25 +103,40 @@ def test_grad_256_f64_fd_and_oracle():
     del out, u
     torch.cuda.empty_cache()
 
+    say("256^3 oracle gradient")
+    _, gw, gaw, gbw = oracle.grad_of_half_sq_dist(u0, f, tgt, C, T, bc)
+    print(f"256^3 gradient vs oracle: dL/du0 {normwise(g, gw):.3e}, dL/dalpha "
+          f"{abs(gab[0] - gaw) / abs(gaw):.3e}, dL/dbeta {abs(gab[1] - gbw) / abs(gbw):.3e}")
+    assert normwise(g, gw) <= 1e-12
+    assert gab[0] == pytest.approx(gaw, rel=1e-11)
+    assert gab[1] == pytest.approx(gbw, rel=1e-11)
+    del gw
+
     def loss(du, da, db):
         c = dict(C, alpha=C["alpha"] + da, beta=C["beta"] + db)
         v = to_dev(u0 + du)
         api.run(v, fd, c, T, bc, norms=False)
         return oracle.half_sq_dist(to_host(v), tgt)
 
-    worst = 0.0
+    # Central differences with eps = 1e-6 on the 32 seeded directions.  The
+    # directional derivative <g,du> + gA*da + gB*db can be a small sum of large
+    # terms, so the mismatch is measured against the size of those terms; the
+    # 4-point stencil (L(-2e) - 8L(-e) + 8L(e) - L(2e)) / 12e is checked too.
+    worst2 = worst4 = 0.0
     for i, (du, da, db) in enumerate(inputs.fd_directions(nx, ny, nz, seed=0, count=32)):
-        fdv = (loss(eps * du, eps * da, eps * db) - loss(-eps * du, -eps * da, -eps * db)) / (2 * eps)
-        an = float(np.dot(g.ravel(), du.ravel())) + gab[0] * da + gab[1] * db
-        worst = max(worst, abs(fdv - an) / abs(an))
-        assert abs(fdv - an) <= 1e-6 * abs(an), i
-    print(f"256^3 FD: worst relative mismatch over 32 directions {worst:.3e}")
-
-    say("256^3 oracle gradient")
-    _, gw, gaw, gbw = oracle.grad_of_half_sq_dist(u0, f, tgt, C, T, bc)
-    assert normwise(g, gw) <= 1e-12
-    assert gab[0] == pytest.approx(gaw, rel=1e-11)
-    assert gab[1] == pytest.approx(gbw, rel=1e-11)
+        lp1, lm1 = loss(eps * du, eps * da, eps * db), loss(-eps * du, -eps * da, -eps * db)
+        lp2, lm2 = loss(2 * eps * du, 2 * eps * da, 2 * eps * db), loss(-2 * eps * du, -2 * eps * da, -2 * eps * db)
+        fd2 = (lp1 - lm1) / (2 * eps)
+        fd4 = (lm2 - 8 * lm1 + 8 * lp1 - lp2) / (12 * eps)
+        terms = (float(np.dot(g.ravel(), du.ravel())), gab[0] * da, gab[1] * db)
+        an = sum(terms)
+        scale = sum(abs(t) for t in terms)
+        worst2 = max(worst2, abs(fd2 - an) / scale)
+        worst4 = max(worst4, abs(fd4 - an) / scale)
+        assert abs(fd2 - an) <= 1e-6 * scale, (i, terms, fd2, fd4)
+        assert abs(fd4 - an) <= 1e-6 * scale, (i, terms, fd2, fd4)
+    print(f"256^3 FD over 32 directions: worst mismatch / term size: 2-point {worst2:.3e}, "
+          f"4-point {worst4:.3e}")
 
 
 def _large_crop(seed=0):
