@@ -35,8 +35,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
-KERNEL_SRC = os.path.join(ROOT, "paper_2107_00555_amd", "csrc", "dcp_kernels.hip")
-COUNTERS = os.path.join(ROOT, "profiles", "stencil_fused_f64_512_counters.md")
+KERNEL_SRCS = {1: os.path.join(ROOT, "paper_2107_00555_amd", "csrc", "dcp_kernels.hip"),
+               2: os.path.join(ROOT, "paper_2107_00555_amd", "csrc", "dcp_tblock.hip")}
+COUNTERS = {1: os.path.join(ROOT, "profiles", "stencil_fused_f64_512_counters.md"),
+            2: os.path.join(ROOT, "profiles", "tb2_fused_f64_512_counters.md")}
+KERNEL_NAMES = {1: "stencil_kernel<double,2,1,4,4,PERIODIC,FWD,norms> (one step per launch)",
+                2: "tb2_kernel<double,2,4,PERIODIC,norms> (two steps per launch)"}
 
 
 def parse():
@@ -49,7 +53,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="also run a plain 1 GiB device copy (counter calibration)")
-    p.add_argument("--tblock", type=int, default=1)
+    p.add_argument("--tblock", type=int, default=2,
+                   help="time steps fused per pass over memory in the headline run (1 or 2)")
     return p.parse_args()
 
 
@@ -87,14 +92,15 @@ def timed(fn, k, w, stream):
     return ev[0].elapsed_time(ev[k]), per, wall
 
 
-def counter_traffic():
-    """HBM bytes per launch of the fused FP64 kernel from the committed
+def counter_traffic(tblock):
+    """HBM bytes per launch of the headline kernel from the committed
     rocprofv3 counter summary, or None if the kernel source changed since."""
-    if not os.path.exists(COUNTERS):
+    path = COUNTERS.get(tblock)
+    if path is None or not os.path.exists(path):
         return None
-    src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    src = hashlib.sha256(open(KERNEL_SRCS[tblock], "rb").read()).hexdigest()
     vals = {}
-    for line in open(COUNTERS):
+    for line in open(path):
         if ":" in line and line.strip().startswith("- "):
             k, v = line.strip()[2:].split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
@@ -110,13 +116,13 @@ def cpu_baseline(u0, f, coeffs, bc):
     """The oracle as it stands, serial, on 2 of the 100 steps of the same
     512^3 workload (full grid)."""
     import oracle
-    T = 2
+    T = 5
     t0 = time.perf_counter()
     oracle.run(u0, f, coeffs, T, bc, norms=True)
     dt = time.perf_counter() - t0
     n = u0.size
     return {"value": n * T / dt / 1e9, "unit": "GLUP/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle_run (serial FP64, every temporary materialised) for 2 of the 100 "
+            "sample": f"oracle_run (serial FP64, every temporary materialised) for {T} of the 100 "
                       f"steps on the full 512^3 periodic grid, {dt:.1f} s"}
 
 
@@ -150,7 +156,7 @@ def main():
 
     # ---------------------------------------------------------- headline
     ws = api.workspace(_lib.workspace_bytes(_lib.OP_RUN, _lib.F64, nx, ny, nz, T=T, norms=True,
-                                            tblock=args.tblock), dev)
+                                            tblock=2), dev)
     res = {}
 
     def fused_step():
@@ -164,18 +170,21 @@ def main():
         torch.cuda.synchronize()
         del uc
 
-    log(f"timing fused f64: T={T}, K={args.steps}, W={args.warmup}")
+    if args.tblock not in (1, 2):
+        raise SystemExit("--tblock must be 1 or 2")
+    log(f"timing fused f64: T={T}, tblock={args.tblock}, K={args.steps}, W={args.warmup}")
     total_ms, per, wall = timed(fused_step, args.steps, args.warmup, stream)
     ms_step = total_ms / args.steps
     value = N * T * args.steps / (total_ms / 1e3) / 1e9
-    launch_ms = total_ms / (args.steps * T)        # average fused-kernel launch (upper bound)
-    bytes_per_launch = 3 * 8 * N                    # read u, read f, write u' (algorithmic)
+    launches = T // args.tblock                     # kernel launches per benchmark step
+    launch_ms = total_ms / (args.steps * launches)  # average launch (includes the tiny finalize)
+    bytes_per_launch = 3 * 8 * N                    # read u, read f, write the result (algorithmic)
     achieved = bytes_per_launch / (launch_ms / 1e3) / 1e9
     med, lo, hi = bootstrap_ci(per)
     e = res["out"]["energy"]
     if not torch.isfinite(e).all():
         raise RuntimeError("non-finite norms in the timed run")
-    traffic = counter_traffic()
+    traffic = counter_traffic(args.tblock)
 
     out = {
         "metric": "GLUP/s and % HBM roofline, fused vs unfused, fwd+adjoint, FP64/FP32 at 512^3",
@@ -191,13 +200,14 @@ def main():
         "dtype": "f64",
         "data": "synthetic (seeded: u0 ~ U[-1,1], f = 8 low-frequency sinusoids)",
         "config": {"workload": "fwd_512_f64: 512^3 float64, periodic, fused forward, T=100 steps "
-                               "per step of the benchmark, FP64 energy+residual norms every step",
+                               "per step of the benchmark, FP64 energy+residual norms every step, "
+                               f"{args.tblock} time step(s) per pass over memory",
                    "grid": [nx, ny, nz], "T": T, "bc": "periodic", "impl": "fused",
                    "tblock": args.tblock, "coeffs": coeffs, "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     "kernel": "stencil_kernel<double,2,1,4,4,PERIODIC,FWD,norms>",
+                     "kernel": KERNEL_NAMES[args.tblock],
                      "bytes_per_launch": bytes_per_launch,
                      "avg_launch_ms": round(launch_ms, 5)},
         "stats": {"median_ms": med, "ci95_ms": [lo, hi], "wall_s": round(wall, 4)},
@@ -215,8 +225,17 @@ def main():
         def frac(ms, bpl, steps=T):
             return (bpl * N * steps / (ms / 1e3) / 1e9) / HBM_PEAK_GBS
 
-        forms["fused_f64"] = {"glups": round(value, 3), "ms": round(ms_step, 3),
-                              "hbm_frac": round(frac(ms_step, 24), 4)}
+        forms[f"fused_f64_tblock{args.tblock}"] = {"glups": round(value, 3), "ms": round(ms_step, 3),
+                                                   "effective_hbm_frac": round(frac(ms_step, 24), 4)}
+        other = 3 - args.tblock
+        uo = u0.clone()
+        log(f"timing fused f64 tblock={other}")
+        ms_o, _, _ = timed(lambda: api.run(uo, f64, coeffs, T, bc, impl="fused", tblock=other, norms=True, ws=ws),
+                           args.steps, 1, stream)
+        ms_o /= args.steps
+        forms[f"fused_f64_tblock{other}"] = {"glups": round(glups(ms_o), 3), "ms": round(ms_o, 3),
+                                             "effective_hbm_frac": round(frac(ms_o, 24), 4)}
+        del uo
 
         # unfused chain, float64
         wsu = api.workspace(_lib.workspace_bytes(_lib.OP_RUN, _lib.F64, nx, ny, nz, T=T, norms=True,
@@ -229,20 +248,26 @@ def main():
         forms["unfused_f64"] = {"glups": round(glups(ms_u), 3), "ms": round(ms_u, 3),
                                 "bytes_per_lup": 21 * 8 + 16,
                                 "hbm_frac": round(frac(ms_u, 21 * 8 + 16), 4)}
-        forms["fused_speedup_over_unfused_f64"] = round(ms_u / ms_step, 3)
+        ms_f = {args.tblock: ms_step, other: ms_o}
+        forms["fused_speedup_over_unfused_f64"] = {"tblock1": round(ms_u / ms_f[1], 3),
+                                                   "tblock2": round(ms_u / ms_f[2], 3)}
         del wsu, uu
 
         # float32 forms
         u32 = u0.to(torch.float32)
         f32 = f64.to(torch.float32)
-        ws32 = api.workspace(_lib.workspace_bytes(_lib.OP_RUN, _lib.F32, nx, ny, nz, T=T, norms=True,
-                                                  impl=_lib.UNFUSED), dev)
-        log("timing fused f32")
-        ms_f32, _, _ = timed(lambda: api.run(u32, f32, coeffs, T, bc, impl="fused", norms=True, ws=ws32),
-                             args.steps, 1, stream)
-        ms_f32 /= args.steps
-        forms["fused_f32"] = {"glups": round(glups(ms_f32), 3), "ms": round(ms_f32, 3),
-                              "hbm_frac": round(frac(ms_f32, 12), 4)}
+        ws32 = api.workspace(max(_lib.workspace_bytes(_lib.OP_RUN, _lib.F32, nx, ny, nz, T=T, norms=True,
+                                                      impl=_lib.UNFUSED),
+                                 _lib.workspace_bytes(_lib.OP_RUN, _lib.F32, nx, ny, nz, T=T, norms=True,
+                                                      tblock=2)), dev)
+        ms32 = {}
+        for tb in (1, 2):
+            log(f"timing fused f32 tblock={tb}")
+            ms_f32, _, _ = timed(lambda: api.run(u32, f32, coeffs, T, bc, impl="fused", tblock=tb, norms=True,
+                                                 ws=ws32), args.steps, 1, stream)
+            ms32[tb] = ms_f32 / args.steps
+            forms[f"fused_f32_tblock{tb}"] = {"glups": round(glups(ms32[tb]), 3), "ms": round(ms32[tb], 3),
+                                              "effective_hbm_frac": round(frac(ms32[tb], 12), 4)}
         u32b = u0.to(torch.float32)
         log("timing unfused f32")
         ms_u32, _, _ = timed(lambda: api.run(u32b, f32, coeffs, T, bc, impl="unfused", norms=True, ws=ws32),
@@ -250,7 +275,8 @@ def main():
         ms_u32 /= kk
         forms["unfused_f32"] = {"glups": round(glups(ms_u32), 3), "ms": round(ms_u32, 3),
                                 "hbm_frac": round(frac(ms_u32, 21 * 4 + 8), 4)}
-        forms["fused_speedup_over_unfused_f32"] = round(ms_u32 / ms_f32, 3)
+        forms["fused_speedup_over_unfused_f32"] = {"tblock1": round(ms_u32 / ms32[1], 3),
+                                                   "tblock2": round(ms_u32 / ms32[2], 3)}
         del ws32, u32b
 
         # adjoint kernel alone: k = 1 (no recomputation), 10 steps
@@ -275,13 +301,13 @@ def main():
         kck = 10
         ug = u0.clone()
         ck = torch.empty((T // kck, nz, ny, nx), dtype=torch.float64, device=dev)
-        wsf = api.workspace(_lib.workspace_bytes(_lib.OP_RUN, _lib.F64, nx, ny, nz, T=T), dev)
+        wsf = api.workspace(_lib.workspace_bytes(_lib.OP_RUN, _lib.F64, nx, ny, nz, T=T, tblock=2), dev)
         wsa = api.workspace(_lib.workspace_bytes(_lib.OP_ADJOINT, _lib.F64, nx, ny, nz, T=T, ckpt_every=kck), dev)
         g = torch.empty_like(u0)
 
         def grad_step():
             ug.copy_(u0)
-            api.run(ug, f64, coeffs, T, bc, norms=False, ckpt_every=kck, ws=wsf, ckpt=ck)
+            api.run(ug, f64, coeffs, T, bc, tblock=args.tblock, norms=False, ckpt_every=kck, ws=wsf, ckpt=ck)
             api.adjoint_run(ck, kck, f64, ug, coeffs, T, bc, ws=wsa, grad_u0=g)
 
         log("timing end-to-end gradient f64")

@@ -6,6 +6,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <initializer_list>
+#include <vector>
 
 #include "dcp.h"
 #include "dcp_internal.h"
@@ -147,7 +148,10 @@ struct RunWs {
     size_t total = 0;
 };
 
-int layout_run(int dtype, int impl, const Geo &g, int32_t T, bool norms, RunWs *w) {
+// LDS of one workgroup on gfx950, the most a two-step pass may plan for.
+constexpr size_t kLdsMax = 160 * 1024;
+
+int layout_run(int dtype, int impl, const Geo &g, int32_t T, int32_t tblock, bool norms, RunWs *w) {
     size_t off = 0;
     if (g.n == 0 || T == 0) {
         w->total = 0;
@@ -160,8 +164,12 @@ int layout_run(int dtype, int impl, const Geo &g, int32_t T, bool norms, RunWs *
         off += 3 * align_up(g.bytes());
     }
     if (norms) {
-        const int nb = impl == DCP_UNFUSED ? ew_norm_blocks(g.n) : max_blocks(dtype, g);
+        int nb = impl == DCP_UNFUSED ? ew_norm_blocks(g.n) : max_blocks(dtype, g);
         if (nb < 0) return DCP_E_SHAPE;
+        TbTile tb;
+        if (impl == DCP_FUSED && tblock >= 2 && tb_plan(dtype, g.nx, g.ny, g.nz, true, kLdsMax, &tb) &&
+            tb.nblk > nb)
+            nb = tb.nblk;
         w->nblk = nb;
         w->partials = off;
         off += align_up((size_t)T * nb * 2 * sizeof(double));
@@ -314,13 +322,16 @@ int step_common(int impl, int dtype, const void *u, const void *f, void *u_out, 
     if (impl == DCP_FUSED) {
         const Tile t = pick_tile(dtype, g, vec_ok_for(dtype, g, {u, f, u_out}));
         DCP_TRY(fused_step(dtype, bc, g, *coeffs, t, u, f, u_out, partials, st));
-        if (norms2) DCP_TRY(launch_finalize(partials, t.nblk, 1, norms2, nullptr, 0, st));
+        if (norms2) DCP_TRY(launch_finalize(partials, t.nblk, t.nblk, 1, norms2, nullptr, 0, st));
     } else {
         void *tmp[3] = {at(ws, w.temps), at(ws, w.temps + align_up(fb)), at(ws, w.temps + 2 * align_up(fb))};
         const bool vok = vec_ok_for(dtype, g, {u, f, u_out, tmp[0], tmp[1], tmp[2]});
         const Tile t = pick_tile(dtype, g, vok);
         DCP_TRY(unfused_step(dtype, bc, g, *coeffs, t, vok, u, f, u_out, tmp, partials, st));
-        if (norms2) DCP_TRY(launch_finalize(partials, ew_norm_blocks(g.n), 1, norms2, nullptr, 0, st));
+        if (norms2) {
+            const int nb = ew_norm_blocks(g.n);
+            DCP_TRY(launch_finalize(partials, nb, nb, 1, norms2, nullptr, 0, st));
+        }
     }
     return DCP_OK;
 }
@@ -346,10 +357,7 @@ const char *dcp_status_string(int status) {
     }
 }
 
-int32_t dcp_max_tblock(int dtype) {
-    (void)dtype;
-    return 1;
-}
+int32_t dcp_max_tblock(int dtype) { return (dtype == DCP_F64 || dtype == DCP_F32) ? 2 : 1; }
 
 int dcp_workspace_bytes(int op, int dtype, int impl, int64_t nx, int64_t ny, int64_t nz, int32_t T,
                         int32_t ckpt_every, int32_t tblock, int norms, size_t *bytes) {
@@ -370,7 +378,7 @@ int dcp_workspace_bytes(int op, int dtype, int impl, int64_t nx, int64_t ny, int
             if (impl != DCP_FUSED && impl != DCP_UNFUSED) return DCP_E_ARG;
             if (T < 0 || tblock < 1 || tblock > dcp_max_tblock(dtype)) return DCP_E_ARG;
             RunWs w;
-            if ((rc = layout_run(dtype, impl, g, T, norms != 0, &w))) return rc;
+            if ((rc = layout_run(dtype, impl, g, T, tblock, norms != 0, &w))) return rc;
             *bytes = w.total;
             return DCP_OK;
         }
@@ -410,7 +418,7 @@ int dcp_run(int dtype, int impl, void *u, const void *f, int64_t nx, int64_t ny,
     if (g.n > 0 && (!u || !f)) return DCP_E_NULL;
     const bool norms = energy || resid;
     RunWs w;
-    if ((rc = layout_run(dtype, impl, g, T, norms, &w))) return rc;
+    if ((rc = layout_run(dtype, impl, g, T, tblock, norms, &w))) return rc;
     if ((rc = check_ws(ws, ws_bytes, w.total))) return rc;
     const size_t fb = g.bytes();
     const int32_t nslots = ckpt ? num_slots(T, ckpt_every) : 0;
@@ -442,27 +450,73 @@ int dcp_run(int dtype, int impl, void *u, const void *f, int64_t nx, int64_t ny,
     bool vok = vec_ok_for(dtype, g, {u, f, buf, tmp[0], tmp[1], tmp[2]});
     for (int32_t c = 0; c < nslots; ++c) vok = vok && aligned16(slot(c));
     const Tile t = pick_tile(dtype, g, vok);
-    const int nblk_red = impl == DCP_UNFUSED ? ew_norm_blocks(g.n) : t.nblk;
+    const int nblk_one = impl == DCP_UNFUSED ? ew_norm_blocks(g.n) : t.nblk;
+    const int stride = w.nblk;  // partial slots per step (>= every kernel's workgroup count)
     double *partials = norms ? reinterpret_cast<double *>(at(ws, w.partials)) : nullptr;
+
+    // two-step passes where the grid allows them and the device has the LDS
+    TbTile tb{};
+    bool use_tb = false;
+    if (impl == DCP_FUSED && tblock >= 2 && T >= 2) {
+        int dev = 0, lds = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
+            use_tb = tb_plan(dtype, g.nx, g.ny, g.nz, vok, (size_t)lds, &tb) && (!norms || tb.nblk <= stride);
+    }
+
+    // workgroup count behind each step's partials, for the fixed-order finalize
+    std::vector<int> step_nblk;
+    if (norms) step_nblk.assign((size_t)T, nblk_one);
 
     if (nslots > 0) DCP_TRY(launch_ew(dtype, EW_COPY, u, nullptr, slot(0), 0.0, g.n, vok, st));
     const void *cur = u;
-    for (int32_t s = 0; s < T; ++s) {
+    for (int32_t s = 0; s < T;) {
+        // a two-step pass may not skip over a checkpoint (its middle state is never stored)
+        const bool mid_ckpt = nslots > 0 && (s + 1) % ckpt_every == 0 && (s + 1) / ckpt_every < nslots;
+        const int32_t len = (use_tb && s + 2 <= T && !mid_ckpt) ? 2 : 1;
+        const int32_t se = s + len;
         void *nxt;
-        const int32_t s1 = s + 1;
-        if (nslots > 0 && s1 % ckpt_every == 0 && s1 / ckpt_every < nslots)
-            nxt = slot(s1 / ckpt_every);
+        if (nslots > 0 && se % ckpt_every == 0 && se / ckpt_every < nslots)
+            nxt = slot(se / ckpt_every);
         else
             nxt = (cur == u) ? buf : u;
-        double *p = partials ? partials + (size_t)s * nblk_red * 2 : nullptr;
-        if (impl == DCP_FUSED)
+        double *p = partials ? partials + (size_t)s * stride * 2 : nullptr;
+        if (len == 2) {
+            TbArgs ta{};
+            ta.u = cur;
+            ta.f = f;
+            ta.out = nxt;
+            ta.part1 = p;
+            ta.part2 = p ? p + (size_t)stride * 2 : nullptr;
+            ta.nx = g.nx;
+            ta.ny = g.ny;
+            ta.nz = g.nz;
+            ta.c0 = coeffs->dt * coeffs->alpha / (coeffs->h * coeffs->h);
+            ta.c1 = coeffs->dt * coeffs->beta;
+            ta.c2 = coeffs->dt * coeffs->gamma;
+            ta.nslab = tb.nslab;
+            ta.zc = tb.zc;
+            DCP_TRY(launch_tb2(dtype, bc, p != nullptr, tb, ta, st));
+            if (norms) step_nblk[s] = step_nblk[s + 1] = tb.nblk;
+        } else if (impl == DCP_FUSED) {
             DCP_TRY(fused_step(dtype, bc, g, *coeffs, t, cur, f, nxt, p, st));
-        else
+        } else {
             DCP_TRY(unfused_step(dtype, bc, g, *coeffs, t, vok, cur, f, nxt, tmp, p, st));
+        }
         cur = nxt;
+        s = se;
     }
     if (cur != u) DCP_TRY(launch_ew(dtype, EW_COPY, cur, nullptr, u, 0.0, g.n, vok, st));
-    if (norms) DCP_TRY(launch_finalize(partials, nblk_red, T, energy, resid, 1, st));
+    if (norms) {
+        // one fixed-order reduction per run of steps that share a workgroup count
+        for (int32_t s0 = 0; s0 < T;) {
+            int32_t s1 = s0 + 1;
+            while (s1 < T && step_nblk[s1] == step_nblk[s0]) ++s1;
+            DCP_TRY(launch_finalize(partials + (size_t)s0 * stride * 2, step_nblk[s0], stride, s1 - s0,
+                                    energy ? energy + s0 : nullptr, resid ? resid + s0 : nullptr, 1, st));
+            s0 = s1;
+        }
+    }
     return DCP_OK;
 }
 
@@ -544,7 +598,7 @@ int dcp_adjoint_run(int dtype, const void *ckpt, int32_t ckpt_every, const void 
             lcur = out;
         }
     }
-    DCP_TRY(launch_finalize(partials, t.nblk, T, sums, nullptr, 2, st));
+    DCP_TRY(launch_finalize(partials, t.nblk, t.nblk, T, sums, nullptr, 2, st));
     DCP_TRY(launch_grad_finalize(sums, T, c.dt / (c.h * c.h), -c.dt, grad_ab, st));
     return DCP_OK;
 }

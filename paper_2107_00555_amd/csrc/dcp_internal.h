@@ -58,11 +58,34 @@ hipError_t launch_ew_norms(int dtype, const void *o, const void *u,
                            double *partials, int64_t n, bool vec_ok,
                            hipStream_t stream);
 
-// Fixed-order reduction of [nsteps][nblk][2] partials.
+// Two fused steps per pass (temporal blocking): full-row slabs of ty rows,
+// zc planes per run, one 1024-lane workgroup per slab-run.
+struct TbArgs {
+    const void *u;      // u_t
+    const void *f;
+    void *out;          // u_{t+2}
+    double *part1;      // [nblk][2] sums of step t+1, or null
+    double *part2;      // [nblk][2] sums of step t+2, or null
+    int64_t nx, ny, nz;
+    double c0, c1, c2;
+    int nslab, zc;
+};
+struct TbTile {
+    int vec, ty, zc, nslab, nruns, nblk;
+    size_t lds_bytes;
+};
+// Plans a two-step pass for this grid; false if the kernel does not apply
+// (rows too long for the LDS budget, or no 16-byte lanes).
+bool tb_plan(int dtype, int64_t nx, int64_t ny, int64_t nz, bool vec_ok, size_t lds_limit,
+             TbTile *t);
+hipError_t launch_tb2(int dtype, int bc, bool reduce, const TbTile &t, const TbArgs &a,
+                      hipStream_t stream);
+
+// Fixed-order reduction of [nsteps][stride][2] partials (first nblk used).
 //   mode 0: out0[0] = sum k=0, out0[1] = sum k=1          (one step)
 //   mode 1: out0[s] = sum k=0, out1[s] = sqrt(sum k=1)   (either may be null)
 //   mode 2: out0[2s+k] = sum k                           (per-step sums)
-hipError_t launch_finalize(const double *partials, int nblk, int nsteps,
+hipError_t launch_finalize(const double *partials, int nblk, int stride, int nsteps,
                            double *out0, double *out1, int mode,
                            hipStream_t stream);
 

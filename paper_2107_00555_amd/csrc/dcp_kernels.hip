@@ -365,41 +365,44 @@ __device__ __forceinline__ void ew_apply(T (&o)[VEC], const T (&x)[VEC], const T
     }
 }
 
+// Element-wise statement over n elements.  Workgroup b streams the
+// contiguous vectors [b*per, min(nv, (b+1)*per)), four 16-byte vectors in
+// flight per lane (contiguous chunks stream faster than a grid-stride walk).
 template <typename T, int VEC, int OPC>
 __global__ void __launch_bounds__(256)
-    ew_kernel(const T *__restrict__ x, const T *__restrict__ y, T *__restrict__ o, T a, int64_t n) {
+    ew_kernel(const T *__restrict__ x, const T *__restrict__ y, T *__restrict__ o, T a, int64_t n, int64_t per) {
     constexpr bool BIN = (OPC == EW_SUB || OPC == EW_ADD);
     constexpr int U = 4;
     const int64_t nv = n / VEC;
-    const int64_t stride = (int64_t)gridDim.x * 256;
-    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    for (; i + (U - 1) * stride < nv; i += U * stride) {
+    const int64_t beg = (int64_t)blockIdx.x * per;
+    const int64_t end = min(nv, beg + per);
+    for (int64_t j = beg + threadIdx.x; j < end; j += 256 * U) {
         T xv[U][VEC], yv[U][VEC], ov[U][VEC];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            load_vec<T, VEC>(xv[u], x + (i + u * stride) * VEC);
-            if constexpr (BIN) load_vec<T, VEC>(yv[u], y + (i + u * stride) * VEC);
-            else zero_vec<T, VEC>(yv[u]);
+            const int64_t i = j + u * 256;
+            if (i < end) {
+                load_vec<T, VEC>(xv[u], x + i * VEC);
+                if constexpr (BIN) load_vec<T, VEC>(yv[u], y + i * VEC);
+                else zero_vec<T, VEC>(yv[u]);
+            }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            ew_apply<T, VEC, OPC>(ov[u], xv[u], yv[u], a);
-            store_vec<T, VEC>(o + (i + u * stride) * VEC, ov[u]);
+            const int64_t i = j + u * 256;
+            if (i < end) {
+                ew_apply<T, VEC, OPC>(ov[u], xv[u], yv[u], a);
+                store_vec<T, VEC>(o + i * VEC, ov[u]);
+            }
         }
     }
-    for (; i < nv; i += stride) {
-        T xv[VEC], yv[VEC], ov[VEC];
-        load_vec<T, VEC>(xv, x + i * VEC);
-        if constexpr (BIN) load_vec<T, VEC>(yv, y + i * VEC);
-        else zero_vec<T, VEC>(yv);
-        ew_apply<T, VEC, OPC>(ov, xv, yv, a);
-        store_vec<T, VEC>(o + i * VEC, ov);
-    }
-    const int64_t t = nv * VEC + (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t < n) {
-        T xv[1] = {x[t]}, yv[1] = {BIN ? y[t] : T(0)}, ov[1];
-        ew_apply<T, 1, OPC>(ov, xv, yv, a);
-        o[t] = ov[0];
+    if (blockIdx.x == 0) {
+        const int64_t t = nv * VEC + threadIdx.x;
+        if (t < n) {
+            T xs[1] = {x[t]}, ys[1] = {BIN ? y[t] : T(0)}, os[1];
+            ew_apply<T, 1, OPC>(os, xs, ys, a);
+            o[t] = os[0];
+        }
     }
 }
 
@@ -456,10 +459,11 @@ __global__ void __launch_bounds__(256)
 }
 
 __global__ void __launch_bounds__(256)
-    finalize_kernel(const double *__restrict__ partials, int nblk, double *out0, double *out1, int mode) {
+    finalize_kernel(const double *__restrict__ partials, int nblk, int stride, double *out0, double *out1,
+                    int mode) {
     __shared__ double red[2][4];
     const int s = blockIdx.x;
-    const double *p = partials + (int64_t)s * nblk * 2;
+    const double *p = partials + (int64_t)s * stride * 2;
     double a0 = 0.0, a1 = 0.0;
     for (int i = threadIdx.x; i < nblk; i += 256) {
         a0 += p[2 * i];
@@ -509,14 +513,19 @@ hipError_t launch_ew_t(int op, const void *x, const void *y, void *o, double a, 
     constexpr int W = 16 / sizeof(T);
     const int vec = vec_ok ? W : 1;
     const int64_t nv = n / vec;
-    int64_t blocks = (nv + 256 * 4 - 1) / (256 * 4);
+    // about eight workgroups per CU, each a contiguous run of 1024-vector strips
+    const int64_t strip = 256 * 4;
+    int64_t per = (nv + 2047) / 2048;
+    per = (per + strip - 1) / strip * strip;
+    if (per < strip) per = strip;
+    int64_t blocks = (nv + per - 1) / per;
     if (blocks < 1) blocks = 1;
-    if (blocks > 8192) blocks = 8192;
     const T *X = static_cast<const T *>(x);
     const T *Y = static_cast<const T *>(y);
     T *O = static_cast<T *>(o);
     const T A = (T)a;
-#define DCP_EW(V, OPC) hipLaunchKernelGGL((ew_kernel<T, V, OPC>), dim3(blocks), dim3(256), 0, st, X, Y, O, A, n)
+#define DCP_EW(V, OPC) \
+    hipLaunchKernelGGL((ew_kernel<T, V, OPC>), dim3(blocks), dim3(256), 0, st, X, Y, O, A, n, per)
     if (vec_ok) {
         switch (op) {
             case EW_POW3: DCP_EW(W, EW_POW3); break;
@@ -586,10 +595,10 @@ hipError_t launch_ew_norms(int dtype, const void *o, const void *u, double *part
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const double *partials, int nblk, int nsteps, double *out0, double *out1, int mode,
-                           hipStream_t st) {
+hipError_t launch_finalize(const double *partials, int nblk, int stride, int nsteps, double *out0, double *out1,
+                           int mode, hipStream_t st) {
     if (nsteps <= 0) return hipSuccess;
-    hipLaunchKernelGGL(finalize_kernel, dim3(nsteps), dim3(256), 0, st, partials, nblk, out0, out1, mode);
+    hipLaunchKernelGGL(finalize_kernel, dim3(nsteps), dim3(256), 0, st, partials, nblk, stride, out0, out1, mode);
     return hipGetLastError();
 }
 

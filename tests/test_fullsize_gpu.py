@@ -39,14 +39,14 @@ def fields_512():
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("impl", ["fused", "unfused"])
-def test_fwd_512_f64_sampled_boxes(fields_512, impl):
+@pytest.mark.parametrize("impl,tblock", [("fused", 2), ("fused", 1), ("unfused", 1)])
+def test_fwd_512_f64_sampled_boxes(fields_512, impl, tblock):
     api = _api()
     u0, f = fields_512
     T, bc = 100, inputs.PERIODIC
-    say("512^3 f64", impl)
+    say("512^3 f64", impl, tblock)
     u = to_dev(u0)
-    out = api.run(u, to_dev(f), C, T, bc, impl=impl, norms=True)
+    out = api.run(u, to_dev(f), C, T, bc, impl=impl, tblock=tblock, norms=True)
     e_last = float(out["energy"][-1])
     e_torch = float(torch.sum(u * u))
     uh = to_host(u)
@@ -76,7 +76,7 @@ def test_fwd_512_f32_sampled_boxes_per_step(fields_512):
     u = to_dev(u0, torch.float32)
     for t in (1, 10, 50, 100):
         say("512^3 f32 to step", t)
-        out = api.run(u, fd, C, t - prev_t, bc, impl="fused", norms=True)
+        out = api.run(u, fd, C, t - prev_t, bc, impl="fused", tblock=2, norms=True)
         prev_t = t
         uh = to_host(u)
         assert float(out["energy"][-1]) == pytest.approx(float(torch.sum(u.double() ** 2)), rel=1e-12)

@@ -192,3 +192,61 @@ def test_python_binding_rejects_bad_tensors():
         api.step(u.cpu(), u.cpu(), BASE, 0)
     with pytest.raises(api.DcpError):
         api.run(u, u.clone(), BASE, 3, 0, tblock=1000)
+
+
+# ------------------------------------------------------------ two-step passes
+TB_SHAPES = [(64, 64, 64), (512, 24, 10), (256, 17, 70), (128, 5, 3), (8, 3, 2), (4, 1, 1),
+             (67, 33, 17), (1024, 9, 6)]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("shape", TB_SHAPES)
+def test_two_step_passes_equal_single_steps_bitwise(shape, bc, dtype):
+    # a two-step pass computes every point with the same operations as the
+    # one-step kernel, so the state must match bit for bit (odd T exercises
+    # the single-step tail; shapes the pass does not support fall back)
+    api = _api()
+    u0, f = rand_fields(shape, 500 + sum(shape))
+    T = 7
+    say("tblock", shape, bc, dtype)
+    fd = to_dev(f, dtype)
+    u1, u2 = to_dev(u0, dtype), to_dev(u0, dtype)
+    o1 = api.run(u1, fd, BASE, T, bc, tblock=1, norms=True)
+    o2 = api.run(u2, fd, BASE, T, bc, tblock=2, norms=True)
+    torch.cuda.synchronize()
+    assert torch.equal(u1, u2)
+    rt = 1e-12 if dtype == torch.float64 else 1e-6
+    assert torch.allclose(o1["energy"], o2["energy"], rtol=rt, atol=0)
+    assert torch.allclose(o1["resid"], o2["resid"], rtol=10 * rt, atol=0)
+
+
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("shape", [(64, 64, 64), (256, 17, 70), (512, 24, 10)])
+def test_two_step_passes_match_oracle(shape, bc):
+    api = _api()
+    u0, f = rand_fields(shape, 600 + sum(shape))
+    T = 8
+    want, e_want, r_want = oracle.run(u0, f, BASE, T, bc)
+    say("tblock vs oracle", shape, bc)
+    u = to_dev(u0)
+    out = api.run(u, to_dev(f), BASE, T, bc, tblock=2, norms=True)
+    torch.cuda.synchronize()
+    assert normwise(to_host(u), want) <= 1e-12
+    np.testing.assert_allclose(to_host(out["energy"]), e_want, rtol=1e-12)
+    np.testing.assert_allclose(to_host(out["resid"]), r_want, rtol=1e-11)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5])
+def test_two_step_passes_with_checkpoints(k):
+    api = _api()
+    shape, T, bc = (128, 20, 18), 9, 1
+    u0, f = rand_fields(shape, 700 + k)
+    fd = to_dev(f)
+    say("tblock ckpt", k)
+    u1, u2 = to_dev(u0), to_dev(u0)
+    o1 = api.run(u1, fd, BASE, T, bc, tblock=1, norms=False, ckpt_every=k)
+    o2 = api.run(u2, fd, BASE, T, bc, tblock=2, norms=False, ckpt_every=k)
+    torch.cuda.synchronize()
+    assert torch.equal(u1, u2)
+    assert torch.equal(o1["ckpt"], o2["ckpt"])
