@@ -209,7 +209,10 @@ def main():
                      "traffic": traffic,
                      "kernel": KERNEL_NAMES[args.tblock],
                      "bytes_per_launch": bytes_per_launch,
-                     "avg_launch_ms": round(launch_ms, 5)},
+                     "avg_launch_ms": round(launch_ms, 5),
+                     # lattice updates x the one-step algorithmic 24 B, over the peak:
+                     # above 1 once a launch fuses more than one time step
+                     "effective_frac": round(value * 24 / HBM_PEAK_GBS, 4)},
         "stats": {"median_ms": med, "ci95_ms": [lo, hi], "wall_s": round(wall, 4)},
     }
 
