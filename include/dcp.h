@@ -103,7 +103,8 @@ typedef struct {
  *   impl        DCP_FUSED or DCP_UNFUSED (DCP_OP_RUN only; ignored otherwise)
  *   T           number of steps (DCP_OP_RUN, DCP_OP_ADJOINT)
  *   ckpt_every  checkpoint interval k (DCP_OP_ADJOINT: >= 1; ignored otherwise)
- *   tblock      steps per pass over memory (DCP_OP_RUN, fused only; 1 = none)
+ *   tblock      steps per pass over memory (DCP_OP_RUN fused, DCP_OP_ADJOINT;
+ *               1 = one step per pass)
  *   norms       nonzero if the call will request norms (energy/resid/norms2)
  * The size is an upper bound valid for any pointer alignment.  Writes it to
  * *bytes (a host pointer).  Returns DCP_OK or an argument error.
@@ -149,8 +150,12 @@ int dcp_step_unfused(int dtype, const void *u, const void *f, void *u_out,
  *   u     [N]   in: u_0; out: u_T
  *   f     [N]   in (must not overlap u)
  *   T           >= 0 (T = 0 leaves u unchanged)
- *   tblock      steps fused per pass over memory (temporal blocking);
+ *   tblock      steps fused per pass over memory (temporal blocking), 1 or 2;
  *               1 = one pass per step.  Values > 1 need impl = DCP_FUSED.
+ *               A two-step pass is used where the grid allows it (x-rows
+ *               that fit the LDS budget, 16-byte aligned fields); the other
+ *               steps run one per pass.  Either way every point is computed
+ *               with the same operations, so u_T is bitwise the same.
  *   energy [T]  out, optional: energy[t-1] = sum u_t^2, t = 1..T (double)
  *   resid  [T]  out, optional: resid[t-1] = sqrt(sum (u_t - u_{t-1})^2)
  *   ckpt        out, optional: ceil(T/k) consecutive fields; slot c holds
@@ -177,19 +182,24 @@ int dcp_run(int dtype, int impl, void *u, const void *f, int64_t nx,
  * kernel, then one fused adjoint kernel per step applies J_t^T (L is
  * symmetric under both boundary rules, so L^T is the same 7-point gather)
  * and accumulates the two parameter sums in double.
+ * With tblock = 2, two adjoint steps (and two recomputed forward steps)
+ * share one pass over memory where the grid allows it; adjoint steps are
+ * paired by global parity, (2m+1, 2m), independently of k.
  *   ckpt        [ceil(T/k) fields] in: as written by dcp_run (same T, k,
  *               coefficients, boundary and dtype)
  *   f      [N]  in
  *   lam_T  [N]  in: dL/du_T
+ *   tblock      1 or 2 (see above; same meaning as in dcp_run)
  *   grad_u0 [N] out: dL/du_0 (must not overlap ckpt, f, lam_T or ws)
  *   grad_ab [2] out, double: {dL/dalpha, dL/dbeta}, reduced in a fixed order,
- *               so the result does not depend on k bit for bit
+ *               so for a given tblock the result does not depend on k bit
+ *               for bit (dL/du_0 does not depend on tblock either)
  */
 int dcp_adjoint_run(int dtype, const void *ckpt, int32_t ckpt_every,
                     const void *f, const void *lam_T, int64_t nx, int64_t ny,
                     int64_t nz, const dcp_coeffs *coeffs, int bc, int32_t T,
-                    void *grad_u0, double *grad_ab, void *ws, size_t ws_bytes,
-                    void *stream);
+                    int32_t tblock, void *grad_u0, double *grad_ab, void *ws,
+                    size_t ws_bytes, void *stream);
 
 /* Static, NUL-terminated description of a dcp_status value. */
 const char *dcp_status_string(int status);

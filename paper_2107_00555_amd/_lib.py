@@ -69,7 +69,7 @@ def lib() -> ctypes.CDLL:
     L.dcp_run.argtypes = [c_int, c_int, vp, vp, i64, i64, i64, cp, c_int, i32, i32, dp, dp, vp, i32,
                           vp, sz, vp]
     L.dcp_run.restype = c_int
-    L.dcp_adjoint_run.argtypes = [c_int, vp, i32, vp, vp, i64, i64, i64, cp, c_int, i32, vp, dp,
+    L.dcp_adjoint_run.argtypes = [c_int, vp, i32, vp, vp, i64, i64, i64, cp, c_int, i32, i32, vp, dp,
                                   vp, sz, vp]
     L.dcp_adjoint_run.restype = c_int
     L.dcp_status_string.argtypes = [c_int]

@@ -96,18 +96,22 @@ def step(u: torch.Tensor, f: torch.Tensor, coeffs, bc, impl="fused", norms: bool
     return out, n2
 
 
-def run(u: torch.Tensor, f: torch.Tensor, coeffs, T: int, bc, impl="fused", tblock: int = 1,
+def run(u: torch.Tensor, f: torch.Tensor, coeffs, T: int, bc, impl="fused", tblock: int | None = None,
         norms: bool = True, ckpt_every: int = 0, ws: torch.Tensor | None = None,
         ckpt: torch.Tensor | None = None):
     """T steps in place on u.  Returns a dict with 'energy' and 'resid'
     (float64 [T] tensors, or None) and 'ckpt' (tensor of ceil(T/k) fields
-    shaped (slots, nz, ny, nx), or None when ckpt_every == 0)."""
+    shaped (slots, nz, ny, nx), or None when ckpt_every == 0).  tblock
+    defaults to 2 (two steps per pass where the grid allows it) for the fused
+    form and 1 for the unfused one."""
     u = _field("u", u)
     f = _field("f", f, u)
     dt = _dtype_code(u)
     nz, ny, nx = u.shape
     c = Coeffs.make(coeffs)
     ic = impl_code(impl)
+    if tblock is None:
+        tblock = 2 if ic == FUSED else 1
     wsb = _lib.workspace_bytes(OP_RUN, dt, nx, ny, nz, T=T, tblock=tblock, norms=norms, impl=ic)
     if ws is None or ws.numel() < wsb:
         ws = workspace(wsb, u.device)
@@ -124,7 +128,7 @@ def run(u: torch.Tensor, f: torch.Tensor, coeffs, T: int, bc, impl="fused", tblo
 
 
 def adjoint_run(ckpt: torch.Tensor | None, ckpt_every: int, f: torch.Tensor, lam_T: torch.Tensor,
-                coeffs, T: int, bc, ws: torch.Tensor | None = None,
+                coeffs, T: int, bc, tblock: int = 2, ws: torch.Tensor | None = None,
                 grad_u0: torch.Tensor | None = None):
     """Gradient through T fused steps from dcp_run's checkpoints.
     Returns (dL/du0, float64 tensor [dL/dalpha, dL/dbeta])."""
@@ -137,7 +141,7 @@ def adjoint_run(ckpt: torch.Tensor | None, ckpt_every: int, f: torch.Tensor, lam
                 or ckpt.numel() < num_slots(T, ckpt_every) * lam_T.numel():
             raise ValueError("ckpt must hold ceil(T/ckpt_every) contiguous fields of the state dtype")
     c = Coeffs.make(coeffs)
-    wsb = _lib.workspace_bytes(OP_ADJOINT, dt, nx, ny, nz, T=T, ckpt_every=ckpt_every)
+    wsb = _lib.workspace_bytes(OP_ADJOINT, dt, nx, ny, nz, T=T, ckpt_every=ckpt_every, tblock=tblock)
     if ws is None or ws.numel() < wsb:
         ws = workspace(wsb, lam_T.device)
     if grad_u0 is None:
@@ -145,5 +149,5 @@ def adjoint_run(ckpt: torch.Tensor | None, ckpt_every: int, f: torch.Tensor, lam
     gab = torch.empty(2, dtype=torch.float64, device=lam_T.device)
     _lib.check("dcp_adjoint_run", _lib.lib().dcp_adjoint_run(
         dt, _ptr(ckpt), int(ckpt_every), _ptr(f), _ptr(lam_T), nx, ny, nz, ctypes.byref(c),
-        bc_code(bc), int(T), _ptr(grad_u0), _ptr(gab), _ptr(ws), wsb, _stream(lam_T.device)))
+        bc_code(bc), int(T), int(tblock), _ptr(grad_u0), _ptr(gab), _ptr(ws), wsb, _stream(lam_T.device)))
     return grad_u0, gab

@@ -18,12 +18,14 @@ def _scalar(x) -> float:
 
 class RD3D(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, u0, f, alpha, beta, gamma, dt, h, T, bc, ckpt_every):
+    def forward(ctx, u0, f, alpha, beta, gamma, dt, h, T, bc, ckpt_every, tblock=2):
         coeffs = dict(alpha=_scalar(alpha), beta=_scalar(beta), gamma=_scalar(gamma),
                       h=float(h), dt=float(dt))
         k = max(1, int(ckpt_every))
         u = u0.detach().contiguous().clone()
-        out = api.run(u, f.detach().contiguous(), coeffs, int(T), bc, norms=False, ckpt_every=k)
+        out = api.run(u, f.detach().contiguous(), coeffs, int(T), bc, tblock=int(tblock), norms=False,
+                      ckpt_every=k)
+        ctx.tblock = int(tblock)
         ctx.coeffs = coeffs
         ctx.T, ctx.bc, ctx.k = int(T), bc, k
         ctx.ckpt = out["ckpt"]
@@ -37,7 +39,7 @@ class RD3D(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_uT):
         g, gab = api.adjoint_run(ctx.ckpt, ctx.k, ctx.f, grad_uT.contiguous(), ctx.coeffs,
-                                 ctx.T, ctx.bc)
+                                 ctx.T, ctx.bc, tblock=ctx.tblock)
         ga = gb = None
         if ctx.needs_input_grad[2] and ctx.alpha_is_tensor:
             dtype, device, shape = ctx.alpha_meta
@@ -46,9 +48,9 @@ class RD3D(torch.autograd.Function):
             dtype, device, shape = ctx.beta_meta
             gb = gab[1].to(dtype=dtype, device=device).reshape(shape)
         gu = g if ctx.needs_input_grad[0] else None
-        return gu, None, ga, gb, None, None, None, None, None, None
+        return gu, None, ga, gb, None, None, None, None, None, None, None
 
 
-def rd3d(u0, f, alpha, beta, gamma, dt, h, T, bc, ckpt_every=10):
+def rd3d(u0, f, alpha, beta, gamma, dt, h, T, bc, ckpt_every=10, tblock=2):
     """u_T after T fused steps from u0, differentiable in u0, alpha and beta."""
-    return RD3D.apply(u0, f, alpha, beta, gamma, dt, h, T, bc, ckpt_every)
+    return RD3D.apply(u0, f, alpha, beta, gamma, dt, h, T, bc, ckpt_every, tblock)

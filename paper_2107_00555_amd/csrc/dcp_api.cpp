@@ -187,15 +187,17 @@ struct AdjWs {
     size_t total = 0;
 };
 
-int layout_adj(int dtype, const Geo &g, int32_t T, int32_t k, AdjWs *w) {
+int layout_adj(int dtype, const Geo &g, int32_t T, int32_t k, int32_t tblock, AdjWs *w) {
     size_t off = 0;
     if (T == 0) {
         w->total = 0;
         return DCP_OK;
     }
     if (g.n > 0) {
-        const int nb = max_blocks(dtype, g);
+        int nb = max_blocks(dtype, g);
         if (nb < 0) return DCP_E_SHAPE;
+        TbTile tb;
+        if (tblock >= 2 && tb_plan(dtype, g.nx, g.ny, g.nz, true, kLdsMax, &tb) && tb.nblk > nb) nb = tb.nblk;
         w->nblk = nb;
         w->lam = off;
         off += 2 * align_up(g.bytes());
@@ -285,6 +287,37 @@ hipError_t unfused_step(int dtype, int bc, const Geo &g, const dcp_coeffs &c, co
     if ((e = launch_ew(dtype, EW_ADD, u, B, out, 0.0, g.n, vec_ok, st))) return e;            // u' = u + t6
     if (partials) return launch_ew_norms(dtype, out, u, partials, g.n, vec_ok, st);
     return hipSuccess;
+}
+
+// A two-step pass u_t -> u_{t+2} (mid receives u_{t+1} when not null).
+hipError_t tb_fwd_pass(int dtype, int bc, const Geo &g, const dcp_coeffs &c, const TbTile &tb, const void *u,
+                       const void *f, void *out, void *mid, double *part1, double *part2, hipStream_t st) {
+    TbArgs ta{};
+    ta.u = u;
+    ta.f = f;
+    ta.out = out;
+    ta.mid = mid;
+    ta.part1 = part1;
+    ta.part2 = part2;
+    ta.nx = g.nx;
+    ta.ny = g.ny;
+    ta.nz = g.nz;
+    ta.c0 = c.dt * c.alpha / (c.h * c.h);
+    ta.c1 = c.dt * c.beta;
+    ta.c2 = c.dt * c.gamma;
+    ta.nslab = tb.nslab;
+    ta.zc = tb.zc;
+    return launch_tb2(dtype, SOP_FWD, bc, part1 != nullptr, tb, ta, st);
+}
+
+// Plans a two-step pass when asked for and supported by the grid and device.
+bool plan_tb(int dtype, const Geo &g, int32_t tblock, bool vok, TbTile *tb) {
+    if (tblock < 2) return false;
+    int dev = 0, lds = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return false;
+    return tb_plan(dtype, g.nx, g.ny, g.nz, vok, (size_t)lds, tb);
 }
 
 bool vec_ok_for(int dtype, const Geo &g, std::initializer_list<const void *> ptrs) {
@@ -384,8 +417,9 @@ int dcp_workspace_bytes(int op, int dtype, int impl, int64_t nx, int64_t ny, int
         }
         case DCP_OP_ADJOINT: {
             if (T < 0 || ckpt_every < 1) return DCP_E_ARG;
+            if (tblock < 1 || tblock > dcp_max_tblock(dtype)) return DCP_E_ARG;
             AdjWs w;
-            if ((rc = layout_adj(dtype, g, T, ckpt_every, &w))) return rc;
+            if ((rc = layout_adj(dtype, g, T, ckpt_every, tblock, &w))) return rc;
             *bytes = w.total;
             return DCP_OK;
         }
@@ -456,47 +490,26 @@ int dcp_run(int dtype, int impl, void *u, const void *f, int64_t nx, int64_t ny,
 
     // two-step passes where the grid allows them and the device has the LDS
     TbTile tb{};
-    bool use_tb = false;
-    if (impl == DCP_FUSED && tblock >= 2 && T >= 2) {
-        int dev = 0, lds = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
-            use_tb = tb_plan(dtype, g.nx, g.ny, g.nz, vok, (size_t)lds, &tb) && (!norms || tb.nblk <= stride);
-    }
+    const bool use_tb = impl == DCP_FUSED && T >= 2 && plan_tb(dtype, g, tblock, vok, &tb) &&
+                        (!norms || tb.nblk <= stride);
 
     // workgroup count behind each step's partials, for the fixed-order finalize
     std::vector<int> step_nblk;
     if (norms) step_nblk.assign((size_t)T, nblk_one);
 
+    auto is_ckpt = [&](int32_t t) { return nslots > 0 && t % ckpt_every == 0 && t / ckpt_every < nslots; };
     if (nslots > 0) DCP_TRY(launch_ew(dtype, EW_COPY, u, nullptr, slot(0), 0.0, g.n, vok, st));
     const void *cur = u;
     for (int32_t s = 0; s < T;) {
-        // a two-step pass may not skip over a checkpoint (its middle state is never stored)
-        const bool mid_ckpt = nslots > 0 && (s + 1) % ckpt_every == 0 && (s + 1) / ckpt_every < nslots;
-        const int32_t len = (use_tb && s + 2 <= T && !mid_ckpt) ? 2 : 1;
+        const int32_t len = (use_tb && s + 2 <= T) ? 2 : 1;
         const int32_t se = s + len;
-        void *nxt;
-        if (nslots > 0 && se % ckpt_every == 0 && se / ckpt_every < nslots)
-            nxt = slot(se / ckpt_every);
-        else
-            nxt = (cur == u) ? buf : u;
+        void *nxt = is_ckpt(se) ? slot(se / ckpt_every) : ((cur == u) ? buf : u);
         double *p = partials ? partials + (size_t)s * stride * 2 : nullptr;
         if (len == 2) {
-            TbArgs ta{};
-            ta.u = cur;
-            ta.f = f;
-            ta.out = nxt;
-            ta.part1 = p;
-            ta.part2 = p ? p + (size_t)stride * 2 : nullptr;
-            ta.nx = g.nx;
-            ta.ny = g.ny;
-            ta.nz = g.nz;
-            ta.c0 = coeffs->dt * coeffs->alpha / (coeffs->h * coeffs->h);
-            ta.c1 = coeffs->dt * coeffs->beta;
-            ta.c2 = coeffs->dt * coeffs->gamma;
-            ta.nslab = tb.nslab;
-            ta.zc = tb.zc;
-            DCP_TRY(launch_tb2(dtype, bc, p != nullptr, tb, ta, st));
+            // a checkpoint at the middle step is stored by the pass itself
+            void *mid = is_ckpt(s + 1) ? slot((s + 1) / ckpt_every) : nullptr;
+            DCP_TRY(tb_fwd_pass(dtype, bc, g, *coeffs, tb, cur, f, nxt, mid, p,
+                                p ? p + (size_t)stride * 2 : nullptr, st));
             if (norms) step_nblk[s] = step_nblk[s + 1] = tb.nblk;
         } else if (impl == DCP_FUSED) {
             DCP_TRY(fused_step(dtype, bc, g, *coeffs, t, cur, f, nxt, p, st));
@@ -521,18 +534,18 @@ int dcp_run(int dtype, int impl, void *u, const void *f, int64_t nx, int64_t ny,
 }
 
 int dcp_adjoint_run(int dtype, const void *ckpt, int32_t ckpt_every, const void *f, const void *lam_T, int64_t nx,
-                    int64_t ny, int64_t nz, const dcp_coeffs *coeffs, int bc, int32_t T, void *grad_u0,
-                    double *grad_ab, void *ws, size_t ws_bytes, void *stream) {
+                    int64_t ny, int64_t nz, const dcp_coeffs *coeffs, int bc, int32_t T, int32_t tblock,
+                    void *grad_u0, double *grad_ab, void *ws, size_t ws_bytes, void *stream) {
     Geo g;
     int rc = check_geo(dtype, nx, ny, nz, &g);
     if (rc) return rc;
     if (bc != DCP_DIRICHLET0 && bc != DCP_PERIODIC) return DCP_E_BC;
     if ((rc = check_coeffs(coeffs))) return rc;
-    if (T < 0 || ckpt_every < 1) return DCP_E_ARG;
+    if (T < 0 || ckpt_every < 1 || tblock < 1 || tblock > dcp_max_tblock(dtype)) return DCP_E_ARG;
     if (!grad_ab) return DCP_E_NULL;
     if (g.n > 0 && (!f || !lam_T || !grad_u0 || (T > 0 && !ckpt))) return DCP_E_NULL;
     AdjWs w;
-    if ((rc = layout_adj(dtype, g, T, ckpt_every, &w))) return rc;
+    if ((rc = layout_adj(dtype, g, T, ckpt_every, tblock, &w))) return rc;
     if ((rc = check_ws(ws, ws_bytes, w.total))) return rc;
     const size_t fb = g.bytes();
     const int32_t nslots = num_slots(T, ckpt_every);
@@ -564,7 +577,10 @@ int dcp_adjoint_run(int dtype, const void *ckpt, int32_t ckpt_every, const void 
     const Tile t = pick_tile(dtype, g, vok);
     double *partials = reinterpret_cast<double *>(at(ws, w.partials));
     double *sums = reinterpret_cast<double *>(at(ws, w.sums));
+    const int stride = w.nblk;
     const dcp_coeffs &c = *coeffs;
+    TbTile tb{};
+    const bool use_tb = plan_tb(dtype, g, tblock, vok, &tb) && tb.nblk <= stride;
 
     StencilArgs aa{};
     aa.nx = g.nx;
@@ -576,29 +592,78 @@ int dcp_adjoint_run(int dtype, const void *ckpt, int32_t ckpt_every, const void 
     aa.tiles_y = t.tiles_y;
     aa.zc = t.zc;
     aa.nblk = t.nblk;
+    TbArgs ta{};
+    ta.nx = g.nx;
+    ta.ny = g.ny;
+    ta.nz = g.nz;
+    ta.c0 = aa.c0;
+    ta.c1 = aa.c1;
+    ta.nslab = tb.nslab;
+    ta.zc = tb.zc;
 
+    // Adjoint steps are taken in pairs (2m+1, 2m) by global parity, whatever
+    // the checkpoint interval: a pair whose lower step lies in the previous
+    // segment waits for that segment (its upper state is a checkpoint slot).
+    // Every step's parameter sums therefore come from the same kernel with the
+    // same tiling for any k, and the gradient does not depend on k bit for bit.
+    std::vector<int> step_nblk((size_t)T, t.nblk);
     const void *lcur = lam_T;
+    int32_t s = T - 1;  // next adjoint step to take
     for (int32_t cs = nslots - 1; cs >= 0; --cs) {
         const int32_t t0 = cs * ckpt_every;
         const int32_t t1 = (t0 + ckpt_every < T) ? t0 + ckpt_every : T;
         // recompute the states u_{t0+1} .. u_{t1-1} of this segment
         const void *prev = slot(cs);
-        for (int32_t j = 1; j < t1 - t0; ++j) {
-            DCP_TRY(fused_step(dtype, bc, g, c, t, prev, f, seg(j - 1), nullptr, st));
-            prev = seg(j - 1);
+        for (int32_t j = 1; j < t1 - t0;) {
+            if (use_tb && j + 1 < t1 - t0) {
+                DCP_TRY(tb_fwd_pass(dtype, bc, g, c, tb, prev, f, seg(j), seg(j - 1), nullptr, nullptr, st));
+                prev = seg(j);
+                j += 2;
+            } else {
+                DCP_TRY(fused_step(dtype, bc, g, c, t, prev, f, seg(j - 1), nullptr, st));
+                prev = seg(j - 1);
+                j += 1;
+            }
         }
-        for (int32_t s = t1 - 1; s >= t0; --s) {
-            const void *ut = (s == t0) ? slot(cs) : static_cast<const void *>(seg(s - t0 - 1));
-            void *out = (s == 0) ? grad_u0 : (lcur == lam[0] ? lam[1] : lam[0]);
-            aa.s = lcur;
-            aa.q = ut;
-            aa.out = out;
-            aa.partials = partials + (size_t)s * t.nblk * 2;
-            DCP_TRY(launch_stencil(dtype, SOP_ADJ, bc, true, t, aa, st));
+        // u_t for t in [t0, t1], the upper end being the next slot
+        auto state = [&](int32_t tt) -> const void * {
+            if (tt % ckpt_every == 0) return slot(tt / ckpt_every);
+            return seg(tt - t0 - 1);
+        };
+        while (s >= t0) {
+            const bool pair = use_tb && (s & 1) && s >= 1;
+            if (pair && s - 1 < t0) break;  // the lower step lives in the previous segment
+            const int32_t se = pair ? s - 1 : s;
+            void *out = (se == 0) ? grad_u0 : (lcur == lam[0] ? lam[1] : lam[0]);
+            if (pair) {
+                ta.u = lcur;
+                ta.f = state(s);
+                ta.g2 = state(s - 1);
+                ta.out = out;
+                ta.mid = nullptr;
+                ta.part1 = partials + (size_t)s * stride * 2;
+                ta.part2 = partials + (size_t)(s - 1) * stride * 2;
+                DCP_TRY(launch_tb2(dtype, SOP_ADJ, bc, true, tb, ta, st));
+                step_nblk[s] = step_nblk[s - 1] = tb.nblk;
+            } else {
+                aa.s = lcur;
+                aa.q = state(s);
+                aa.out = out;
+                aa.partials = partials + (size_t)s * stride * 2;
+                DCP_TRY(launch_stencil(dtype, SOP_ADJ, bc, true, t, aa, st));
+            }
             lcur = out;
+            s = se - 1;
         }
     }
-    DCP_TRY(launch_finalize(partials, t.nblk, t.nblk, T, sums, nullptr, 2, st));
+    // per-step sums in a fixed order, then over the steps in a fixed order
+    for (int32_t s0 = 0; s0 < T;) {
+        int32_t s1 = s0 + 1;
+        while (s1 < T && step_nblk[s1] == step_nblk[s0]) ++s1;
+        DCP_TRY(launch_finalize(partials + (size_t)s0 * stride * 2, step_nblk[s0], stride, s1 - s0,
+                                sums + 2 * (size_t)s0, nullptr, 2, st));
+        s0 = s1;
+    }
     DCP_TRY(launch_grad_finalize(sums, T, c.dt / (c.h * c.h), -c.dt, grad_ab, st));
     return DCP_OK;
 }

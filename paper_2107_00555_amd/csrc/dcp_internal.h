@@ -60,25 +60,31 @@ hipError_t launch_ew_norms(int dtype, const void *o, const void *u,
 
 // Two fused steps per pass (temporal blocking): full-row slabs of ty rows,
 // zc planes per run, one 1024-lane workgroup per slab-run.
+//   SOP_FWD: u = u_t, f = f, out = u_{t+2}, mid = u_{t+1} or null;
+//            part1/part2 = norms of steps t+1 / t+2 (or null)
+//   SOP_ADJ: u = lambda_{t+1}, f = u_t, g2 = u_{t-1}, out = lambda_{t-1};
+//            part1/part2 = parameter sums of steps t / t-1
 struct TbArgs {
-    const void *u;      // u_t
+    const void *u;
     const void *f;
-    void *out;          // u_{t+2}
-    double *part1;      // [nblk][2] sums of step t+1, or null
-    double *part2;      // [nblk][2] sums of step t+2, or null
+    const void *g2;
+    void *out;
+    void *mid;
+    double *part1;      // [nblk][2]
+    double *part2;      // [nblk][2]
     int64_t nx, ny, nz;
     double c0, c1, c2;
     int nslab, zc;
 };
 struct TbTile {
-    int vec, ty, zc, nslab, nruns, nblk;
+    int vec, ty, nt, km, zc, nslab, nruns, nblk;
     size_t lds_bytes;
 };
 // Plans a two-step pass for this grid; false if the kernel does not apply
 // (rows too long for the LDS budget, or no 16-byte lanes).
 bool tb_plan(int dtype, int64_t nx, int64_t ny, int64_t nz, bool vec_ok, size_t lds_limit,
              TbTile *t);
-hipError_t launch_tb2(int dtype, int bc, bool reduce, const TbTile &t, const TbArgs &a,
+hipError_t launch_tb2(int dtype, int op, int bc, bool reduce, const TbTile &t, const TbArgs &a,
                       hipStream_t stream);
 
 // Fixed-order reduction of [nsteps][stride][2] partials (first nblk used).

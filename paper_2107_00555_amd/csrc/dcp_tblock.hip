@@ -26,13 +26,13 @@
 // Every point is computed with exactly the same operations, in the same
 // order, as the one-step kernel, so a pass equals two one-step launches bit
 // for bit; the two steps' norms are reduced over the owned points only.
+#include <cstdlib>
+
 #include "dcp_internal.h"
 
 namespace dcp {
 namespace {
 
-constexpr int kTbThreads = 1024;
-constexpr int kTbKmax = 2;  // 16-byte chunks per lane per level
 
 template <typename T, int N>
 struct TbVec {
@@ -93,10 +93,13 @@ __device__ __forceinline__ int tb_xcd_remap(int b, int nb) {
     return xcd * per + min(xcd, rem) + j;
 }
 
-// The one-step update of a point, operation for operation as in the
+// The one-step updates of a point, operation for operation as in the
 // one-step kernel: s6 = ((xm + xp) + (ym + yp)) + (zm + zp).
+//   forward: u + c0*(s6 - 6u) - c1*u^3 + c2*f        (c1 = dt*beta)
+//   adjoint: l + c0*(s6 - 6l) - c1*u^2*l             (c1 = 3*dt*beta), with the
+//            parameter sums (s6 - 6l)*u and l*u^3 in double
 template <typename T>
-__device__ __forceinline__ T tb_point(T c, T xm, T xp, T ym, T yp, T zm, T zp, T fq, T C0, T C1, T C2) {
+__device__ __forceinline__ T tb_fwd(T c, T xm, T xp, T ym, T yp, T zm, T zp, T fq, T C0, T C1, T C2) {
     const T s6 = ((xm + xp) + (ym + yp)) + (zm + zp);
     const T lapn = fma(T(-6), c, s6);
     T acc = fma(C2, fq, c);
@@ -105,8 +108,30 @@ __device__ __forceinline__ T tb_point(T c, T xm, T xp, T ym, T yp, T zm, T zp, T
     return acc;
 }
 
-template <typename T, int VEC, int TY, int BC, bool RED>
-__global__ void __launch_bounds__(kTbThreads) tb2_kernel(TbArgs a) {
+template <typename T>
+__device__ __forceinline__ T tb_adj(T c, T xm, T xp, T ym, T yp, T zm, T zp, T uq, T C0, T C1, double &sa,
+                                    double &sb) {
+    const T s6 = ((xm + xp) + (ym + yp)) + (zm + zp);
+    const T lapn = fma(T(-6), c, s6);
+    T acc = fma(C0, lapn, c);
+    acc = fma(-(C1 * uq) * uq, c, acc);
+    const double du = (double)uq;
+    sa = (double)lapn * du;
+    sb = (double)c * (du * du * du);
+    return acc;
+}
+
+// NT lanes per workgroup; each lane owns up to KM 16-byte chunks of the
+// level-0 frame (KM * NT >= (TY + 4) * nx / VEC, checked by the planner).
+// OP = SOP_FWD: level 0 = u_t, point operand f at both levels, sums = the
+//   norms of steps t+1 and t+2; MID also stores u_{t+1} on the owned points.
+// OP = SOP_ADJ: level 0 = lambda_{t+1}, point operands u_t (level 1) and
+//   u_{t-1} (level 2), sums = the parameter sums of steps t and t-1.
+template <typename T, int VEC, int TY, int NT, int KM, int BC, int OP, bool RED, bool MID>
+__global__ void __launch_bounds__(NT) tb2_kernel(TbArgs a) {
+    constexpr int kTbThreads = NT;
+    constexpr int kTbKmax = KM;
+    constexpr bool ADJ = (OP == SOP_ADJ);
     extern __shared__ __align__(16) unsigned char tb_smem[];
     constexpr int R0 = TY + 4;  // level-0 rows: global rows y0-2 .. y0+TY+1
     constexpr int R1 = TY + 2;  // level-1 rows: global rows y0-1 .. y0+TY
@@ -125,8 +150,10 @@ __global__ void __launch_bounds__(kTbThreads) tb2_kernel(TbArgs a) {
     const int z1 = min(nz, z0 + a.zc);
 
     const T *__restrict__ U = static_cast<const T *>(a.u);
-    const T *__restrict__ F = static_cast<const T *>(a.f);
+    const T *__restrict__ QA = static_cast<const T *>(a.f);   // level-1 point operand
+    const T *__restrict__ QB = static_cast<const T *>(a.g2);  // level-2 point operand (adjoint)
     T *__restrict__ O = static_cast<T *>(a.out);
+    T *__restrict__ M = static_cast<T *>(a.mid);
     const T C0 = (T)a.c0, C1 = (T)a.c1, C2 = (T)a.c2;
 
     // The lane's points: chunk k covers level-0 frame row r = idx / CH and
@@ -160,12 +187,22 @@ __global__ void __launch_bounds__(kTbThreads) tb2_kernel(TbArgs a) {
                 tb_zero<T, VEC>(d[k]);
         }
     };
-    auto load_f = [&](int zq, T (&d)[kTbKmax][VEC]) {
+    // point operand of level 1 on the level-1 rows, of level 2 on the owned rows
+    auto load_qa = [&](int zq, T (&d)[kTbKmax][VEC]) {
         const int zr = tb_wrap<BC>(zq, nz);
 #pragma unroll
         for (int k = 0; k < kTbKmax; ++k) {
             if ((flags[k] & 2u) && gofs[k] >= 0 && zr >= 0)
-                tb_load<T, VEC>(d[k], F + (int64_t)zr * sz + gofs[k]);
+                tb_load<T, VEC>(d[k], QA + (int64_t)zr * sz + gofs[k]);
+            else
+                tb_zero<T, VEC>(d[k]);
+        }
+    };
+    auto load_qb = [&](int zq, T (&d)[kTbKmax][VEC]) {
+#pragma unroll
+        for (int k = 0; k < kTbKmax; ++k) {
+            if ((flags[k] & 4u) && zq >= 0 && zq < nz)
+                tb_load<T, VEC>(d[k], QB + (int64_t)zq * sz + gofs[k]);
             else
                 tb_zero<T, VEC>(d[k]);
         }
@@ -183,10 +220,12 @@ __global__ void __launch_bounds__(kTbThreads) tb2_kernel(TbArgs a) {
     };
 
     // register queues: level 0 at q-1, q+1 and the prefetched q+2; level 1 at
-    // q-2 and q; f at q-1, q and the prefetched q+1 (the centres live in LDS)
+    // q-2 and q; level-1 point operand at q and the prefetched q+1; level-2
+    // point operand at q-1 (and, for the adjoint, the prefetched q); the
+    // centres live in LDS
     T am[kTbKmax][VEC], ap[kTbKmax][VEC], an[kTbKmax][VEC];
     T bm[kTbKmax][VEC], bn[kTbKmax][VEC];
-    T fm[kTbKmax][VEC], fc[kTbKmax][VEC], fn[kTbKmax][VEC];
+    T qbm[kTbKmax][VEC], qac[kTbKmax][VEC], qan[kTbKmax][VEC], qbn[kTbKmax][VEC];
     double e1 = 0.0, r1 = 0.0, e2 = 0.0, r2 = 0.0;
 
     T ac0[kTbKmax][VEC];  // level 0 at the first plane, written to LDS in the first iteration
@@ -194,27 +233,30 @@ __global__ void __launch_bounds__(kTbThreads) tb2_kernel(TbArgs a) {
         load_u(z0 - 2, am);
         load_u(z0 - 1, ac0);
         load_u(z0, ap);
-        load_f(z0 - 1, fc);
+        load_qa(z0 - 1, qac);
     }
 #pragma unroll
     for (int k = 0; k < kTbKmax; ++k) {
         tb_zero<T, VEC>(bm[k]);
-        tb_zero<T, VEC>(fm[k]);
+        tb_zero<T, VEC>(qbm[k]);
+        tb_zero<T, VEC>(qbn[k]);
         if (flags[k] & 1u) tb_store<T, VEC>(L0 + lofs[k], ac0[k]);
     }
 
     for (int q = z0 - 1; z0 < z1 && q <= z1; ++q) {
         // LDS holds level 0 at plane q (written before the barrier); prefetch
-        // level 0 at q+2 and f at q+1
+        // level 0 at q+2 and the point operands
         const bool more = q < z1;
         if (more) {
             load_u(q + 2, an);
-            load_f(q + 1, fn);
+            load_qa(q + 1, qan);
+            if constexpr (ADJ) load_qb(q, qbn);
         }
         __syncthreads();
 
-        // stage A: level 1 (step t+1) at plane q
+        // stage A: level 1 at plane q
         const int qr = tb_wrap<BC>(q, nz);
+        const bool owned_plane = q >= z0 && q < z1;
         T *L1w = L1[q & 1];
 #pragma unroll
         for (int k = 0; k < kTbKmax; ++k) {
@@ -223,6 +265,7 @@ __global__ void __launch_bounds__(kTbThreads) tb2_kernel(TbArgs a) {
             const int xo = (int)(flags[k] >> 3);
             T c[VEC];
             tb_load<T, VEC>(c, L0 + o);
+            const bool sum_here = (flags[k] & 4u) && owned_plane;
             if (BC == 0 && (qr < 0 || gofs[k] < 0)) {
                 tb_zero<T, VEC>(bn[k]);
             } else {
@@ -234,13 +277,25 @@ __global__ void __launch_bounds__(kTbThreads) tb2_kernel(TbArgs a) {
                 for (int e = 0; e < VEC; ++e) {
                     const T xm = e == 0 ? lft : c[e > 0 ? e - 1 : 0];
                     const T xp = e == VEC - 1 ? rgt : c[e + 1 < VEC ? e + 1 : e];
-                    bn[k][e] = tb_point<T>(c[e], xm, xp, ym[e], yp[e], am[k][e], ap[k][e], fc[k][e],
-                                           C0, C1, C2);
+                    if constexpr (ADJ) {
+                        double sa, sb;
+                        bn[k][e] = tb_adj<T>(c[e], xm, xp, ym[e], yp[e], am[k][e], ap[k][e], qac[k][e], C0, C1,
+                                             sa, sb);
+                        if (sum_here) {
+                            e1 += sa;
+                            r1 += sb;
+                        }
+                    } else {
+                        bn[k][e] = tb_fwd<T>(c[e], xm, xp, ym[e], yp[e], am[k][e], ap[k][e], qac[k][e], C0, C1,
+                                             C2);
+                    }
                 }
             }
             tb_store<T, VEC>(L1w + o - nx, bn[k]);
-            if constexpr (RED) {
-                if ((flags[k] & 4u) && q >= z0 && q < z1) {
+            if constexpr (MID)
+                if (sum_here) tb_store<T, VEC>(M + (int64_t)q * sz + gofs[k], bn[k]);
+            if constexpr (RED && !ADJ) {
+                if (sum_here) {
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) {
                         const double d = (double)bn[k][e];
@@ -252,7 +307,7 @@ __global__ void __launch_bounds__(kTbThreads) tb2_kernel(TbArgs a) {
             }
         }
 
-        // stage B: level 2 (step t+2) at plane q-1, from level 1 at q-2, q-1, q
+        // stage B: level 2 at plane q-1, from level 1 at q-2, q-1, q
         if (q - 1 >= z0) {
             const T *L1r = L1[(q - 1) & 1];
 #pragma unroll
@@ -269,11 +324,19 @@ __global__ void __launch_bounds__(kTbThreads) tb2_kernel(TbArgs a) {
                 for (int e = 0; e < VEC; ++e) {
                     const T xm = e == 0 ? lft : c[e > 0 ? e - 1 : 0];
                     const T xp = e == VEC - 1 ? rgt : c[e + 1 < VEC ? e + 1 : e];
-                    res[e] = tb_point<T>(c[e], xm, xp, ym[e], yp[e], bm[k][e], bn[k][e], fm[k][e],
-                                         C0, C1, C2);
+                    if constexpr (ADJ) {
+                        double sa, sb;
+                        res[e] = tb_adj<T>(c[e], xm, xp, ym[e], yp[e], bm[k][e], bn[k][e], qbm[k][e], C0, C1,
+                                           sa, sb);
+                        e2 += sa;
+                        r2 += sb;
+                    } else {
+                        res[e] = tb_fwd<T>(c[e], xm, xp, ym[e], yp[e], bm[k][e], bn[k][e], qbm[k][e], C0, C1,
+                                           C2);
+                    }
                 }
                 tb_store<T, VEC>(O + (int64_t)(q - 1) * sz + gofs[k], res);
-                if constexpr (RED) {
+                if constexpr (RED && !ADJ) {
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) {
                         const double d = (double)res[e];
@@ -297,8 +360,9 @@ __global__ void __launch_bounds__(kTbThreads) tb2_kernel(TbArgs a) {
         for (int k = 0; k < kTbKmax; ++k) {
             if (flags[k] & 1u) tb_store<T, VEC>(L0 + lofs[k], ap[k]);  // level 0 at q+1
             tb_copy<T, VEC>(ap[k], an[k]);
-            tb_copy<T, VEC>(fm[k], fc[k]);
-            tb_copy<T, VEC>(fc[k], fn[k]);
+            if constexpr (ADJ) tb_copy<T, VEC>(qbm[k], qbn[k]);
+            else tb_copy<T, VEC>(qbm[k], qac[k]);
+            tb_copy<T, VEC>(qac[k], qan[k]);
         }
     }
 
@@ -334,28 +398,46 @@ __global__ void __launch_bounds__(kTbThreads) tb2_kernel(TbArgs a) {
     }
 }
 
-template <typename T, int VEC, int TY>
-hipError_t tb_launch_t(int bc, bool reduce, const TbTile &t, const TbArgs &a, hipStream_t st) {
-    const dim3 grid(t.nblk), block(kTbThreads);
+template <typename T, int VEC, int TY, int NT, int KM>
+hipError_t tb_launch_t(int op, int bc, bool reduce, bool mid, const TbTile &t, const TbArgs &a,
+                       hipStream_t st) {
+    const dim3 grid(t.nblk), block(NT);
     const size_t lds = t.lds_bytes;
-#define DCP_TB(BCV, REDV)                                                                             \
+#define DCP_TB(BCV, OPV, REDV, MIDV)                                                                  \
     do {                                                                                              \
-        auto fn = tb2_kernel<T, VEC, TY, BCV, REDV>;                                                  \
+        auto fn = tb2_kernel<T, VEC, TY, NT, KM, BCV, OPV, REDV, MIDV>;                               \
         hipError_t e_ = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),                       \
                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);    \
         if (e_ != hipSuccess) return e_;                                                              \
         hipLaunchKernelGGL(fn, grid, block, lds, st, a);                                              \
     } while (0)
-    if (bc == 0) {
-        if (reduce) DCP_TB(0, true);
-        else DCP_TB(0, false);
+    if (op == SOP_ADJ) {
+        if (bc == 0) DCP_TB(0, SOP_ADJ, true, false);
+        else DCP_TB(1, SOP_ADJ, true, false);
+    } else if (mid) {
+        if (bc == 0) DCP_TB(0, SOP_FWD, false, true);
+        else DCP_TB(1, SOP_FWD, false, true);
+    } else if (bc == 0) {
+        if (reduce) DCP_TB(0, SOP_FWD, true, false);
+        else DCP_TB(0, SOP_FWD, false, false);
     } else {
-        if (reduce) DCP_TB(1, true);
-        else DCP_TB(1, false);
+        if (reduce) DCP_TB(1, SOP_FWD, true, false);
+        else DCP_TB(1, SOP_FWD, false, false);
     }
 #undef DCP_TB
     return hipGetLastError();
 }
+
+// Compiled configurations (slab rows, lanes, chunks per lane), in order of
+// preference: taller slabs recompute fewer halo rows.  Each chunk costs about
+// 40 VGPRs (eight queued 16-byte vectors plus addressing), so two chunks per
+// lane at 1024 lanes is the most that stays out of scratch: 8-row slabs fit
+// rows of up to 170 chunks (FP32 nx <= 680), 4-row slabs up to 256 chunks.
+struct TbCfg {
+    int ty, nt, km;
+};
+constexpr TbCfg kTbCfgs[] = {{8, 1024, 2}, {4, 1024, 2}};
+constexpr int kNumTbCfgs = sizeof(kTbCfgs) / sizeof(kTbCfgs[0]);
 
 }  // namespace
 
@@ -365,14 +447,16 @@ bool tb_plan(int dtype, int64_t nx, int64_t ny, int64_t nz, bool vec_ok, size_t 
     if (!vec_ok || nx <= 0 || ny <= 0 || nz <= 0 || nx % vec != 0) return false;
     if (nx > (1 << 24) || nx * ny > (int64_t)INT32_MAX || nz > (1 << 29) || ny > (1 << 29)) return false;
     const int64_t ch = nx / vec;
-    // taller slabs when the rows are short enough (fewer halo rows per slab)
-    const int tys[2] = {8, 4};
-    for (int ty : tys) {
-        const size_t lds = (size_t)((ty + 4) + 2 * (ty + 2)) * (size_t)nx * esz;
-        if ((ty + 4) * ch > (int64_t)kTbKmax * kTbThreads) continue;
+    const char *forced = std::getenv("DCP_TB_CFG");  // tuning runs only
+    const int only = (forced && *forced) ? std::atoi(forced) : -1;
+    for (int i = 0; i < kNumTbCfgs; ++i) {
+        if (only >= 0 && i != only) continue;
+        const TbCfg c = kTbCfgs[i];
+        const size_t lds = (size_t)((c.ty + 4) + 2 * (c.ty + 2)) * (size_t)nx * esz;
+        if ((c.ty + 4) * ch > (int64_t)c.km * c.nt) continue;
         if (lds > lds_limit) continue;
-        if (lds < (size_t)(kTbThreads / 64) * 4 * sizeof(double)) continue;
-        const int64_t nslab = (ny + ty - 1) / ty;
+        if (lds < (size_t)(c.nt / 64) * 4 * sizeof(double)) continue;
+        const int64_t nslab = (ny + c.ty - 1) / c.ty;
         if (nslab > 65536) return false;
         // one workgroup per CU: 256 workgroups in all
         int64_t runs = 256 / nslab;
@@ -381,7 +465,9 @@ bool tb_plan(int dtype, int64_t nx, int64_t ny, int64_t nz, bool vec_ok, size_t 
         int64_t zc = (nz + runs - 1) / runs;
         runs = (nz + zc - 1) / zc;
         t->vec = vec;
-        t->ty = ty;
+        t->ty = c.ty;
+        t->nt = c.nt;
+        t->km = c.km;
         t->zc = (int)zc;
         t->nslab = (int)nslab;
         t->nruns = (int)runs;
@@ -392,13 +478,15 @@ bool tb_plan(int dtype, int64_t nx, int64_t ny, int64_t nz, bool vec_ok, size_t 
     return false;
 }
 
-hipError_t launch_tb2(int dtype, int bc, bool reduce, const TbTile &t, const TbArgs &a, hipStream_t st) {
+hipError_t launch_tb2(int dtype, int op, int bc, bool reduce, const TbTile &t, const TbArgs &a, hipStream_t st) {
+    if (t.nt != 1024 || t.km != 2) return hipErrorInvalidValue;
+    const bool mid = op == SOP_FWD && a.mid != nullptr;
     if (dtype == 0) {
-        if (t.ty == 8) return tb_launch_t<double, 2, 8>(bc, reduce, t, a, st);
-        return tb_launch_t<double, 2, 4>(bc, reduce, t, a, st);
+        if (t.ty == 8) return tb_launch_t<double, 2, 8, 1024, 2>(op, bc, reduce, mid, t, a, st);
+        return tb_launch_t<double, 2, 4, 1024, 2>(op, bc, reduce, mid, t, a, st);
     }
-    if (t.ty == 8) return tb_launch_t<float, 4, 8>(bc, reduce, t, a, st);
-    return tb_launch_t<float, 4, 4>(bc, reduce, t, a, st);
+    if (t.ty == 8) return tb_launch_t<float, 4, 8, 1024, 2>(op, bc, reduce, mid, t, a, st);
+    return tb_launch_t<float, 4, 4, 1024, 2>(op, bc, reduce, mid, t, a, st);
 }
 
 }  // namespace dcp

@@ -142,11 +142,11 @@ def test_run_argument_errors(L):
     assert run_call(L, dtype=-1) == -3
 
 
-def adj_call(L, dtype=0, ckpt=0x50000000, k=2, f=F, lam=U, n=(8, 8, 8), c=None, bc=0, T=4, g=O,
-             gab=0x60000000, ws=WS, wsb=1 << 26):
+def adj_call(L, dtype=0, ckpt=0x50000000, k=2, f=F, lam=U, n=(8, 8, 8), c=None, bc=0, T=4, tb=1,
+             g=O, gab=0x60000000, ws=WS, wsb=1 << 26):
     c = coeffs(L) if c is None else c
     return L.lib().dcp_adjoint_run(dtype, ckpt, k, f, lam, n[0], n[1], n[2], ctypes.byref(c), bc,
-                                   T, g, gab, ws, wsb, None)
+                                   T, tb, g, gab, ws, wsb, None)
 
 
 def test_adjoint_argument_errors(L):
@@ -159,3 +159,5 @@ def test_adjoint_argument_errors(L):
     assert adj_call(L, wsb=8) == -6
     assert adj_call(L, ws=F) == -7
     assert adj_call(L, c=coeffs(L, beta=float("-inf"))) == -5
+    assert adj_call(L, tb=0) == -5
+    assert adj_call(L, tb=3) == -5

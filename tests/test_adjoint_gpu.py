@@ -59,15 +59,20 @@ def test_adjoint_f32_matches_oracle(bc):
     assert gab[1] == pytest.approx(wb, rel=1e-5)
 
 
+@pytest.mark.parametrize("tblock", [1, 2])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_gradient_is_bitwise_independent_of_checkpoint_interval(dtype):
-    shape, T, bc = (72, 30, 20), 10, 1
+def test_gradient_is_bitwise_independent_of_checkpoint_interval(dtype, tblock):
+    api = _api()
+    shape, T, bc = (128, 30, 20), 11, 1
     u0, f = rand_fields(shape, 18)
     lam = np.random.default_rng(3).uniform(-1, 1, u0.shape)
-    say("k independence", dtype)
+    say("k independence", dtype, tblock)
     ref = None
-    for k in (1, 3, 4, 10, 25):
-        g, gab = gpu_grad(u0, f, lam, T, bc, k, dtype)
+    for k in (1, 2, 3, 4, 10, 25):
+        u = to_dev(u0, dtype)
+        fd = to_dev(f, dtype)
+        out = api.run(u, fd, BASE, T, bc, tblock=tblock, norms=False, ckpt_every=k)
+        g, gab = api.adjoint_run(out["ckpt"], k, fd, to_dev(lam, dtype), BASE, T, bc, tblock=tblock)
         if ref is None:
             ref = (g, gab)
         else:
@@ -141,3 +146,40 @@ def test_rd3d_backward_matches_oracle():
     assert normwise(to_host(u.grad), gw) <= 1e-12
     assert float(alpha.grad) == pytest.approx(gaw, rel=1e-11)
     assert float(beta.grad) == pytest.approx(gbw, rel=1e-11)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("bc", [0, 1])
+@pytest.mark.parametrize("shape,T,k", [((64, 24, 20), 9, 4), ((128, 20, 18), 8, 3), ((256, 9, 11), 7, 1),
+                                       ((512, 12, 6), 6, 6), ((67, 20, 9), 5, 2)])
+def test_two_step_adjoint_equals_single_steps(shape, T, k, bc, dtype):
+    # paired adjoint passes apply exactly the one-step operations: dL/du0 is
+    # bitwise the same; the parameter sums differ only by summation order
+    api = _api()
+    u0, f = rand_fields(shape, 800 + sum(shape))
+    lam = np.random.default_rng(8).uniform(-1, 1, u0.shape)
+    fd = to_dev(f, dtype)
+    say("two-step adjoint", shape, T, k, bc, dtype)
+    res = {}
+    for tb in (1, 2):
+        u = to_dev(u0, dtype)
+        out = api.run(u, fd, BASE, T, bc, tblock=tb, norms=False, ckpt_every=k)
+        res[tb] = api.adjoint_run(out["ckpt"], k, fd, to_dev(lam, dtype), BASE, T, bc, tblock=tb)
+    torch.cuda.synchronize()
+    assert torch.equal(res[1][0], res[2][0])
+    assert torch.allclose(res[1][1], res[2][1], rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_two_step_adjoint_matches_oracle(bc):
+    shape, T, k = (128, 24, 20), 9, 4
+    u0, f = rand_fields(shape, 900 + bc)
+    lam = np.random.default_rng(9).uniform(-1, 1, u0.shape)
+    want, wa, wb = oracle.adjoint(u0, f, lam, BASE, T, bc)
+    say("two-step adjoint vs oracle", bc)
+    g, gab = gpu_grad(u0, f, lam, T, bc, k)
+    torch.cuda.synchronize()
+    assert normwise(to_host(g), want) <= 1e-12
+    gab = to_host(gab)
+    assert gab[0] == pytest.approx(wa, rel=1e-11)
+    assert gab[1] == pytest.approx(wb, rel=1e-11)
