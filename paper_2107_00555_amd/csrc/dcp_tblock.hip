@@ -430,13 +430,17 @@ hipError_t tb_launch_t(int op, int bc, bool reduce, bool mid, const TbTile &t, c
 
 // Compiled configurations (slab rows, lanes, chunks per lane), in order of
 // preference: taller slabs recompute fewer halo rows.  Each chunk costs about
-// 40 VGPRs (eight queued 16-byte vectors plus addressing), so two chunks per
-// lane at 1024 lanes is the most that stays out of scratch: 8-row slabs fit
-// rows of up to 170 chunks (FP32 nx <= 680), 4-row slabs up to 256 chunks.
+// 40-50 VGPRs (eight or nine queued 16-byte vectors plus addressing).  512
+// lanes with four chunks each (2 waves per SIMD, up to 256 VGPRs) stay out of
+// scratch and measured faster than 1024 lanes with two chunks (128 VGPRs,
+// which spills in the adjoint): at 512^3, FP64 adjoint 305 vs 248 GLUP/s,
+// FP32 adjoint 611 vs 393.  8-row slabs fit rows of up to 170 chunks
+// (FP32 nx <= 680), 4-row slabs up to 256 chunks (FP64 nx <= 512,
+// FP32 nx <= 1024); the LDS budget is checked separately.
 struct TbCfg {
     int ty, nt, km;
 };
-constexpr TbCfg kTbCfgs[] = {{8, 1024, 2}, {4, 1024, 2}};
+constexpr TbCfg kTbCfgs[] = {{8, 512, 4}, {4, 512, 4}, {8, 1024, 2}, {4, 1024, 2}};
 constexpr int kNumTbCfgs = sizeof(kTbCfgs) / sizeof(kTbCfgs[0]);
 
 }  // namespace
@@ -479,14 +483,23 @@ bool tb_plan(int dtype, int64_t nx, int64_t ny, int64_t nz, bool vec_ok, size_t 
 }
 
 hipError_t launch_tb2(int dtype, int op, int bc, bool reduce, const TbTile &t, const TbArgs &a, hipStream_t st) {
-    if (t.nt != 1024 || t.km != 2) return hipErrorInvalidValue;
     const bool mid = op == SOP_FWD && a.mid != nullptr;
+    const bool n1024 = t.nt == 1024 && t.km == 2, n512 = t.nt == 512 && t.km == 4;
+    if (!n1024 && !n512) return hipErrorInvalidValue;
     if (dtype == 0) {
-        if (t.ty == 8) return tb_launch_t<double, 2, 8, 1024, 2>(op, bc, reduce, mid, t, a, st);
-        return tb_launch_t<double, 2, 4, 1024, 2>(op, bc, reduce, mid, t, a, st);
+        if (n1024) {
+            if (t.ty == 8) return tb_launch_t<double, 2, 8, 1024, 2>(op, bc, reduce, mid, t, a, st);
+            return tb_launch_t<double, 2, 4, 1024, 2>(op, bc, reduce, mid, t, a, st);
+        }
+        if (t.ty == 8) return tb_launch_t<double, 2, 8, 512, 4>(op, bc, reduce, mid, t, a, st);
+        return tb_launch_t<double, 2, 4, 512, 4>(op, bc, reduce, mid, t, a, st);
     }
-    if (t.ty == 8) return tb_launch_t<float, 4, 8, 1024, 2>(op, bc, reduce, mid, t, a, st);
-    return tb_launch_t<float, 4, 4, 1024, 2>(op, bc, reduce, mid, t, a, st);
+    if (n1024) {
+        if (t.ty == 8) return tb_launch_t<float, 4, 8, 1024, 2>(op, bc, reduce, mid, t, a, st);
+        return tb_launch_t<float, 4, 4, 1024, 2>(op, bc, reduce, mid, t, a, st);
+    }
+    if (t.ty == 8) return tb_launch_t<float, 4, 8, 512, 4>(op, bc, reduce, mid, t, a, st);
+    return tb_launch_t<float, 4, 4, 512, 4>(op, bc, reduce, mid, t, a, st);
 }
 
 }  // namespace dcp
