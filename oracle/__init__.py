@@ -1,14 +1,16 @@
-"""Plain serial FP64 CPU oracle for the reaction-diffusion array program.
+"""Plain serial FP64 CPU oracle for the reaction-diffusion array program and
+for the two Jacobi stencil programs the paper lists.
 
 TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
 benchmark's CPU-baseline leg may import this package; the GPU library never
 does, and this package imports nothing from it.  The arithmetic lives in
-``rd3d_oracle.c`` (built with gcc, no FMA contraction); this module only
-marshals NumPy arrays into it.  Where each function comes from in the paper
+``rd3d_oracle.c`` and ``jacobi_oracle.c`` (built with gcc, no FMA
+contraction); this module only marshals NumPy arrays into them.  Where each function comes from in the paper
 is stated in the C source.
 
-Arrays are float64, C-contiguous, shape ``(nz, ny, nx)`` (x fastest).
-Boundary modes: 0 = ghost-zero Dirichlet, 1 = periodic.
+Reaction-diffusion arrays are float64, C-contiguous, shape ``(nz, ny, nx)``
+(x fastest); boundary modes: 0 = ghost-zero Dirichlet, 1 = periodic.
+Jacobi arrays are float64 vectors (1D) or C-order (n0, n1) matrices (2D).
 """
 from __future__ import annotations
 
@@ -19,7 +21,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "rd3d_oracle.c")
+_SRCS = [os.path.join(_HERE, "rd3d_oracle.c"), os.path.join(_HERE, "jacobi_oracle.c")]
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -33,7 +35,7 @@ def build(force: bool = True) -> str:
         tmp = _LIB_PATH + ".tmp"
         subprocess.check_call([
             "gcc", "-std=c11", "-O3", "-ffp-contract=off", "-fno-fast-math",
-            "-fPIC", "-shared", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm",
+            "-fPIC", "-shared", "-Wall", "-Wextra", "-o", tmp, *_SRCS, "-lm",
         ])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -60,6 +62,11 @@ def _load():
         lib.oracle_adjoint.restype = ctypes.c_int
         lib.oracle_half_sq_dist.argtypes = [i64, dp, dp]
         lib.oracle_half_sq_dist.restype = d
+        i32 = ctypes.c_int32
+        lib.oracle_jacobi_1d_box.argtypes = [i32, i64, i64, i64, dp, dp]
+        lib.oracle_jacobi_1d_box.restype = ctypes.c_int
+        lib.oracle_jacobi_2d_box.argtypes = [i32, i64, i64, i64, i64, i64, i64, dp, dp]
+        lib.oracle_jacobi_2d_box.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -152,3 +159,56 @@ def grad_of_half_sq_dist(u0, f, u_tgt, coeffs: dict, T: int, bc: int):
     lam_T = uT - _field(u_tgt)
     g, ga, gb = adjoint(u0, f, lam_T, coeffs, T, bc)
     return loss, g, ga, gb
+
+
+def _vec(a, ndim: int) -> np.ndarray:
+    a = np.array(a, dtype=np.float64, order="C", copy=True)
+    if a.ndim != ndim:
+        raise ValueError(f"expected a {ndim}-D array, got shape {a.shape}")
+    return a
+
+
+def jacobi_1d(tsteps: int, A, B):
+    """The jacobi_1d listing (Sec. 2.2) on copies of A and B; returns (A, B)."""
+    A = _vec(A, 1)
+    B = _vec(B, 1)
+    if A.shape != B.shape:
+        raise ValueError("A and B must have the same length")
+    return jacobi_1d_box(tsteps, A.size, 0, A, B)
+
+
+def jacobi_1d_box(tsteps: int, n: int, c0: int, A, B):
+    """The window [c0, c0+len(A)) of a length-n jacobi_1d run (see the C
+    source for which cells are exact); works on copies, returns (A, B)."""
+    A = _vec(A, 1)
+    B = _vec(B, 1)
+    if A.shape != B.shape:
+        raise ValueError("A and B must have the same length")
+    rc = _load().oracle_jacobi_1d_box(int(tsteps), int(n), int(c0), A.size, _ptr(A), _ptr(B))
+    if rc != 0:
+        raise ValueError(f"oracle_jacobi_1d_box failed with code {rc}")
+    return A, B
+
+
+def jacobi_2d(tsteps: int, A, B):
+    """The jacobi_2d listing (Sec. 4.3) on copies of A and B; returns (A, B)."""
+    A = _vec(A, 2)
+    B = _vec(B, 2)
+    if A.shape != B.shape:
+        raise ValueError("A and B must have the same shape")
+    return jacobi_2d_box(tsteps, A.shape[0], A.shape[1], 0, 0, A, B)
+
+
+def jacobi_2d_box(tsteps: int, n0: int, n1: int, r0: int, c0: int, A, B):
+    """The window starting at (r0, c0) of an n0 x n1 jacobi_2d run; works on
+    copies, returns (A, B)."""
+    A = _vec(A, 2)
+    B = _vec(B, 2)
+    if A.shape != B.shape:
+        raise ValueError("A and B must have the same shape")
+    h0, h1 = A.shape
+    rc = _load().oracle_jacobi_2d_box(int(tsteps), int(n0), int(n1), int(r0), int(c0), h0, h1,
+                                      _ptr(A), _ptr(B))
+    if rc != 0:
+        raise ValueError(f"oracle_jacobi_2d_box failed with code {rc}")
+    return A, B

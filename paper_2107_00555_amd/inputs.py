@@ -1,4 +1,4 @@
-"""Seeded synthetic inputs for the reaction-diffusion workloads.
+"""Seeded synthetic inputs for the reaction-diffusion and Jacobi workloads.
 
 This module holds the random input generators only: none of the program's
 arithmetic.  Both the GPU path's tests/benchmark and the CPU oracle consume
@@ -12,6 +12,8 @@ with a fixed stream id ``s``:
     1  f              source field
     2  u_tgt          loss target
     3  FD directions  finite-difference probes
+    4  A              Jacobi programs, first array
+    5  B              Jacobi programs, second array
 
 Arrays are float64, C order, shape ``(nz, ny, nx)`` (x is the fastest axis).
 Float32 workloads cast these once (round to nearest even).
@@ -24,6 +26,8 @@ STREAM_U0 = 0
 STREAM_F = 1
 STREAM_TGT = 2
 STREAM_FD = 3
+STREAM_JA = 4
+STREAM_JB = 5
 
 
 def rng(seed: int, stream: int) -> np.random.Generator:
@@ -138,3 +142,48 @@ def make_fields(workload: str | dict, seed: int = 0, shape=None):
 def target(nx: int, ny: int, nz: int, seed: int = 0) -> np.ndarray:
     """u_tgt ~ U[-1,1] for the gradient workloads."""
     return uniform(nx, ny, nz, seed, STREAM_TGT)
+
+
+# The two Jacobi listings (jacobi_1d in Sec. 2.2, jacobi_2d in Sec. 4.3),
+# float64 in and out.  "paper" sizes are the initial problem sizes of the
+# distributed-benchmark table in Sec. 4.4 (one process: T=1000 with N=24000,
+# and T=1000 with N=1300); "p1296" sizes are those problems weak-scaled, by
+# the table's scaling factors (N*S in 1D, N*sqrt(S) in 2D), to the largest
+# run of that section, S = 1296 processes, all on one GPU.  The paper gives
+# no input values; A and B are i.i.d. U[-1, 1] here.
+JACOBI_WORKLOADS = {
+    "jacobi_1d_paper": dict(dims=1, n=24000, tsteps=1000),
+    "jacobi_2d_paper": dict(dims=2, n=1300, tsteps=1000),
+    "jacobi_1d_p1296": dict(dims=1, n=24000 * 1296, tsteps=1000),
+    "jacobi_2d_p1296": dict(dims=2, n=1300 * 36, tsteps=1000),
+}
+
+
+def jacobi_shape(dims: int, n: int, n1: int | None = None) -> tuple:
+    if dims == 1:
+        return (int(n),)
+    return (int(n), int(n if n1 is None else n1))
+
+
+def jacobi_fields(dims: int, n: int, seed: int = 0, n1: int | None = None):
+    """(A, B) ~ U[-1, 1], float64 NumPy arrays of shape (n,) or (n, n1)."""
+    shape = jacobi_shape(dims, n, n1)
+    return (rng(seed, STREAM_JA).uniform(-1.0, 1.0, size=shape),
+            rng(seed, STREAM_JB).uniform(-1.0, 1.0, size=shape))
+
+
+def jacobi_fields_device(dims: int, n: int, seed: int = 0, device="cuda", n1: int | None = None):
+    """(A, B) ~ U[-1, 1] as float64 torch tensors drawn on the device (for
+    sizes too large to draw on the host); a different sequence from
+    jacobi_fields, reproducible for a given seed and device type."""
+    import torch
+    shape = jacobi_shape(dims, n, n1)
+    out = []
+    for stream in (STREAM_JA, STREAM_JB):
+        g = torch.Generator(device=device)
+        g.manual_seed(int(np.random.SeedSequence([int(seed), stream]).generate_state(1, np.uint64)[0]
+                          & 0x7FFFFFFFFFFFFFFF))
+        t = torch.empty(shape, dtype=torch.float64, device=device)
+        t.uniform_(-1.0, 1.0, generator=g)
+        out.append(t)
+    return out[0], out[1]
