@@ -16,7 +16,9 @@ N*T*K / seconds / 1e9).
 In the same run (--forms all, the default) every other form of the metric
 is timed on the same inputs, each in its own event-timed region: the
 unfused single-operator chain, the float32 forms, the adjoint kernel and
-the end-to-end gradient (forward with checkpoints + checkpointed adjoint).
+the end-to-end gradient (forward with checkpoints + checkpointed adjoint);
+then the two Jacobi listings (jacobi_1d, jacobi_2d) at the paper's problem
+sizes and weak-scaled to 1296 processes, with and without temporal blocking.
 
 Prints ONE JSON line.  With --gpus N, N > 1, it exits with a message: this
 benchmark runs on one GPU only.
@@ -35,6 +37,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+# MI355X FP64 vector: 78.6 TFLOP/s counting an FMA as two flops; adds and
+# multiplies issue at the same instruction rate and count one flop each.
+FP64_NONFMA_PEAK_TFLOPS = 78.6 / 2
 KERNEL_SRCS = {1: os.path.join(ROOT, "paper_2107_00555_amd", "csrc", "dcp_kernels.hip"),
                2: os.path.join(ROOT, "paper_2107_00555_amd", "csrc", "dcp_tblock.hip")}
 COUNTERS = {1: os.path.join(ROOT, "profiles", "stencil_fused_f64_512_counters.md"),
@@ -319,6 +324,46 @@ def main():
         forms["gradient_f64_T100_k10"] = {"ms": round(ms_g, 3),
                                           "ms_over_forward": round(ms_g / ms_step, 3)}
         del ck, wsf, wsa, g, ug, u32, f32
+
+    # ------------------------------------------------ the Jacobi listings
+    if args.forms == "all":
+        torch.cuda.empty_cache()
+        jac = {}
+        out["forms"]["jacobi"] = jac
+        for name, w in inputs.JACOBI_WORKLOADS.items():
+            dims, n, Tj = w["dims"], w["n"], w["tsteps"]
+            n1 = n if dims == 2 else 1
+            a, b = inputs.jacobi_fields_device(dims, n, seed=args.seed, device=dev)
+            wsj = api.workspace(_lib.jacobi_workspace_bytes(dims, n, n1, Tj, 0), dev)
+            run_j = api.jacobi_1d if dims == 1 else api.jacobi_2d
+            N = a.numel()
+            lups = (n - 2) ** dims * 2 * (Tj - 1)   # interior points x half-steps
+            flops = 3 if dims == 1 else 5           # adds and one multiply per update
+            big = N > (1 << 26)
+            kj = 3 if big else max(5, kk)
+            log(f"timing {name} (n={n}, T={Tj})")
+            # each call continues from the arrays the previous one left
+            ms_j, per_j, _ = timed(lambda: run_j(a, b, Tj, 0, ws=wsj), kj, 1, stream)
+            ms_j /= kj
+            passes, halo = _lib.jacobi_plan(dims, n, n1, Tj, 0)
+            pass_ms = ms_j / passes
+            ent = {"dims": dims, "n": n, "tsteps": Tj, "passes": passes, "halfsteps_per_pass": halo,
+                   "ms": round(ms_j, 4), "ms_median_ci95": [round(x, 4) for x in bootstrap_ci(per_j)],
+                   "glups": round(lups / (ms_j * 1e-3) / 1e9, 2),
+                   # a pass reads A and writes A (16 B per element); the last also writes B
+                   "hbm_per_pass": {"bytes": 16 * N, "gbs": round(16 * N / (pass_ms * 1e-3) / 1e9, 1),
+                                    "frac": round(16 * N / (pass_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+                   "alu_useful": {"tflops": round(lups * flops / (ms_j * 1e-3) / 1e12, 3),
+                                  "peak": FP64_NONFMA_PEAK_TFLOPS,
+                                  "frac": round(lups * flops / (ms_j * 1e-3) / 1e12 / FP64_NONFMA_PEAK_TFLOPS, 4)}}
+            if not big:
+                ms_1, _, _ = timed(lambda: run_j(a, b, Tj, 1, ws=wsj), 3, 1, stream)
+                ms_1 /= 3
+                ent["ms_one_halfstep_per_pass"] = round(ms_1, 3)
+                ent["speedup_over_one_halfstep_per_pass"] = round(ms_1 / ms_j, 2)
+            jac[name] = ent
+            del a, b, wsj
+            torch.cuda.empty_cache()
 
     # --------------------------------------------------------- CPU oracle
     if not args.no_cpu_baseline:

@@ -201,6 +201,61 @@ int dcp_adjoint_run(int dtype, const void *ckpt, int32_t ckpt_every,
                     int32_t tblock, void *grad_u0, double *grad_ab, void *ws,
                     size_t ws_bytes, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * The Jacobi stencil programs the paper lists: jacobi_1d (Sec. 2.2, the
+ * static-symbolic-typing example) and jacobi_2d (Sec. 4.3, the shared-memory
+ * program that the local-view example distributes).  Both take two float64
+ * arrays A and B and a step count TSTEPS and run the listings' time loop
+ * for t = 1 .. TSTEPS-1 (no pass when TSTEPS <= 1); each pass
+ *   1D:  B[i] = 0.33333 * ((A[i-1] + A[i]) + A[i+1])    for 1 <= i <= n-2,
+ *        then A[i] from B the same way;
+ *   2D:  B[i][j] = 0.2 * ((((A[i][j] + A[i][j-1]) + A[i][j+1]) + A[i+1][j])
+ *                         + A[i-1][j])           for 1 <= i <= n0-2,
+ *                                                    1 <= j <= n1-2,
+ *        then A[i][j] from B the same way.
+ * The weights are the listings' literals; the sums are added in the
+ * listings' left-to-right order and every operation rounds once, so A and B
+ * equal a plain serial evaluation bit for bit, for every tblock.  Elements
+ * outside the interior (the ends; the outer rows and columns) are never
+ * written.  An array with no interior (n < 3; n0 < 3 or n1 < 3) is left
+ * unchanged.
+ *
+ * Layout.  1D: n contiguous doubles.  2D: row-major n0 x n1 (element (i, j)
+ *   at i*n1 + j, j contiguous); the listing's case is n0 = n1 = N.
+ * A, B  [N]  in/out, device, caller-owned; must not overlap each other.
+ * tblock     at most this many half-steps per pass over memory (temporal
+ *            blocking): 0 = the library's default; 1D: 1..256, 2D: 1..16.
+ *            2D arrays need n1 < 2^30.
+ * ws         device workspace of dcp_jacobi_workspace_bytes(dims, n0, n1,
+ *            tsteps, tblock, &bytes) bytes (n0 = n and n1 ignored for
+ *            dims = 1); two
+ *            array copies when any pass runs, else 0 and ws may be NULL);
+ *            must not overlap A or B.
+ * Errors as for the other entry points: DCP_E_SHAPE (negative extent or
+ *   overflow), DCP_E_ARG (tblock out of range, dims not 1 or 2), DCP_E_NULL,
+ *   DCP_E_ALIAS, DCP_E_WORKSPACE, all before any work is enqueued;
+ *   DCP_E_HIP for a failed launch.
+ */
+int dcp_jacobi_workspace_bytes(int dims, int64_t n0, int64_t n1,
+                               int32_t tsteps, int32_t tblock, size_t *bytes);
+
+/*
+ * The pass schedule a call with these arguments would run: *passes = number
+ * of passes over memory (0 when nothing runs), *halo = the most half-steps in
+ * one pass (host pointers).  Passes are even in number; when tblock >= 2 and
+ * TSTEPS >= 3 each holds whole iterations (an even number of half-steps) and
+ * only the last one stores B.
+ */
+int dcp_jacobi_plan(int dims, int64_t n0, int64_t n1, int32_t tsteps,
+                    int32_t tblock, int64_t *passes, int32_t *halo);
+
+int dcp_jacobi_1d(int32_t tsteps, double *A, double *B, int64_t n,
+                  int32_t tblock, void *ws, size_t ws_bytes, void *stream);
+
+int dcp_jacobi_2d(int32_t tsteps, double *A, double *B, int64_t n0,
+                  int64_t n1, int32_t tblock, void *ws, size_t ws_bytes,
+                  void *stream);
+
 /* Static, NUL-terminated description of a dcp_status value. */
 const char *dcp_status_string(int status);
 

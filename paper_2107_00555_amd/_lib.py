@@ -76,6 +76,14 @@ def lib() -> ctypes.CDLL:
     L.dcp_status_string.restype = ctypes.c_char_p
     L.dcp_max_tblock.argtypes = [c_int]
     L.dcp_max_tblock.restype = i32
+    L.dcp_jacobi_workspace_bytes.argtypes = [c_int, i64, i64, i32, i32, ctypes.POINTER(sz)]
+    L.dcp_jacobi_workspace_bytes.restype = c_int
+    L.dcp_jacobi_plan.argtypes = [c_int, i64, i64, i32, i32, ctypes.POINTER(i64), ctypes.POINTER(i32)]
+    L.dcp_jacobi_plan.restype = c_int
+    L.dcp_jacobi_1d.argtypes = [i32, vp, vp, i64, i32, vp, sz, vp]
+    L.dcp_jacobi_1d.restype = c_int
+    L.dcp_jacobi_2d.argtypes = [i32, vp, vp, i64, i64, i32, vp, sz, vp]
+    L.dcp_jacobi_2d.restype = c_int
     _lib = L
     return L
 
@@ -93,3 +101,18 @@ def workspace_bytes(op: int, dtype: int, nx: int, ny: int, nz: int, T: int = 0,
           lib().dcp_workspace_bytes(op, dtype, impl, nx, ny, nz, T, ckpt_every, tblock,
                                     int(bool(norms)), ctypes.byref(out)))
     return out.value
+
+
+def jacobi_workspace_bytes(dims: int, n0: int, n1: int, tsteps: int, tblock: int = 0) -> int:
+    out = ctypes.c_size_t(0)
+    check("dcp_jacobi_workspace_bytes",
+          lib().dcp_jacobi_workspace_bytes(dims, n0, n1, tsteps, tblock, ctypes.byref(out)))
+    return out.value
+
+
+def jacobi_plan(dims: int, n0: int, n1: int, tsteps: int, tblock: int = 0) -> tuple[int, int]:
+    """(passes over memory, most half-steps in one pass) of a Jacobi call."""
+    passes, halo = ctypes.c_int64(0), ctypes.c_int32(0)
+    check("dcp_jacobi_plan",
+          lib().dcp_jacobi_plan(dims, n0, n1, tsteps, tblock, ctypes.byref(passes), ctypes.byref(halo)))
+    return passes.value, halo.value

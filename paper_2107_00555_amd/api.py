@@ -16,7 +16,8 @@ from ._lib import (DIRICHLET0, F32, F64, FUSED, OP_ADJOINT, OP_RUN, OP_STEP_FUSE
                    OP_STEP_UNFUSED, PERIODIC, UNFUSED, Coeffs, DcpError)
 
 __all__ = ["Coeffs", "DcpError", "DIRICHLET0", "PERIODIC", "FUSED", "UNFUSED",
-           "step", "run", "adjoint_run", "workspace", "num_slots", "bc_code", "impl_code"]
+           "step", "run", "adjoint_run", "workspace", "num_slots", "bc_code", "impl_code",
+           "jacobi_1d", "jacobi_2d"]
 
 
 def bc_code(bc) -> int:
@@ -151,3 +152,45 @@ def adjoint_run(ckpt: torch.Tensor | None, ckpt_every: int, f: torch.Tensor, lam
         dt, _ptr(ckpt), int(ckpt_every), _ptr(f), _ptr(lam_T), nx, ny, nz, ctypes.byref(c),
         bc_code(bc), int(T), int(tblock), _ptr(grad_u0), _ptr(gab), _ptr(ws), wsb, _stream(lam_T.device)))
     return grad_u0, gab
+
+
+def _jacobi_arrays(A: torch.Tensor, B: torch.Tensor, dims: int):
+    for name, t in (("A", A), ("B", B)):
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        if t.device.type != "cuda":
+            raise ValueError(f"{name} must be a GPU tensor (got device {t.device})")
+        if t.dtype != torch.float64:
+            raise TypeError(f"{name} must be float64, got {t.dtype}")
+        if t.dim() != dims:
+            raise ValueError(f"{name} must be {dims}-D, got shape {tuple(t.shape)}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+    if A.shape != B.shape or A.device != B.device:
+        raise ValueError("A and B must have the same shape and device")
+
+
+def jacobi_1d(A: torch.Tensor, B: torch.Tensor, tsteps: int, tblock: int = 0,
+              ws: torch.Tensor | None = None):
+    """The jacobi_1d listing, in place on float64 vectors A and B."""
+    _jacobi_arrays(A, B, 1)
+    n = A.shape[0]
+    wsb = _lib.jacobi_workspace_bytes(1, n, 1, tsteps, tblock)
+    if ws is None or ws.numel() < wsb:
+        ws = workspace(wsb, A.device)
+    _lib.check("dcp_jacobi_1d", _lib.lib().dcp_jacobi_1d(
+        int(tsteps), _ptr(A), _ptr(B), n, int(tblock), _ptr(ws), wsb, _stream(A.device)))
+    return A, B
+
+
+def jacobi_2d(A: torch.Tensor, B: torch.Tensor, tsteps: int, tblock: int = 0,
+              ws: torch.Tensor | None = None):
+    """The jacobi_2d listing, in place on float64 (n0, n1) arrays A and B."""
+    _jacobi_arrays(A, B, 2)
+    n0, n1 = A.shape
+    wsb = _lib.jacobi_workspace_bytes(2, n0, n1, tsteps, tblock)
+    if ws is None or ws.numel() < wsb:
+        ws = workspace(wsb, A.device)
+    _lib.check("dcp_jacobi_2d", _lib.lib().dcp_jacobi_2d(
+        int(tsteps), _ptr(A), _ptr(B), n0, n1, int(tblock), _ptr(ws), wsb, _stream(A.device)))
+    return A, B

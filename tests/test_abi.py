@@ -161,3 +161,80 @@ def test_adjoint_argument_errors(L):
     assert adj_call(L, c=coeffs(L, beta=float("-inf"))) == -5
     assert adj_call(L, tb=0) == -5
     assert adj_call(L, tb=3) == -5
+
+
+# ------------------------------------------------------------------ Jacobi
+JA, JB = 0x70000000, 0x78000000
+
+
+def test_jacobi_workspace_sizes(L):
+    assert L.jacobi_workspace_bytes(1, 24000, 1, 1000) == 2 * 24000 * 8   # two array copies
+    assert L.jacobi_workspace_bytes(2, 1300, 1300, 1000) == 2 * 1300 * 1300 * 8 + 2 * 128
+    assert L.jacobi_workspace_bytes(2, 1300, 7, 1000, 16) == 2 * 72960   # 72800 B rounded up to 256
+    for args in ((1, 24000, 1, 1), (1, 24000, 1, 0), (1, 24000, 1, -3), (1, 2, 1, 50),
+                 (2, 2, 900, 50), (2, 900, 2, 50), (2, 0, 0, 50)):
+        assert L.jacobi_workspace_bytes(*args) == 0   # no pass runs
+
+
+@pytest.mark.parametrize("args,code", [
+    ((3, 10, 10, 5, 0), -5), ((0, 10, 10, 5, 0), -5),   # dims
+    ((1, -1, 1, 5, 0), -2), ((2, 10, -1, 5, 0), -2),     # extents
+    ((2, 1 << 40, 1 << 40, 5, 0), -2),                   # size overflow
+    ((1, 10, 1, 5, -1), -5), ((1, 10, 1, 5, 257), -5), ((2, 10, 10, 5, 17), -5),  # tblock
+])
+def test_jacobi_workspace_errors(L, args, code):
+    out = ctypes.c_size_t(0)
+    assert L.lib().dcp_jacobi_workspace_bytes(*args, ctypes.byref(out)) == code
+
+
+def j1(L, T=5, A=JA, B=JB, n=100, tb=0, ws=WS, wsb=1 << 26):
+    return L.lib().dcp_jacobi_1d(T, A, B, n, tb, ws, wsb, None)
+
+
+def j2(L, T=5, A=JA, B=JB, n0=40, n1=50, tb=0, ws=WS, wsb=1 << 26):
+    return L.lib().dcp_jacobi_2d(T, A, B, n0, n1, tb, ws, wsb, None)
+
+
+def test_jacobi_argument_errors(L):
+    for call in (j1, j2):
+        assert call(L, A=None) == -1
+        assert call(L, B=None) == -1
+        assert call(L, B=JA + 8) == -7          # B overlaps A
+        assert call(L, ws=JB + 64) == -7        # workspace overlaps B
+        assert call(L, wsb=64) == -6
+        assert call(L, ws=None) == -1
+        assert call(L, tb=-1) == -5
+    assert j1(L, tb=257) == -5
+    assert j2(L, tb=17) == -5
+    assert j1(L, n=-4) == -2
+    assert j2(L, n1=-4) == -2
+
+
+def test_jacobi_noop_calls_enqueue_nothing(L):
+    # no pass runs: OK without a workspace and without touching the arrays
+    # (the addresses are not device memory, so any access would fail)
+    assert j1(L, T=1, ws=None, wsb=0) == 0
+    assert j1(L, T=-7, ws=None, wsb=0) == 0
+    assert j1(L, n=2, ws=None, wsb=0) == 0
+    assert j1(L, n=0, A=None, B=None, ws=None, wsb=0) == 0
+    assert j2(L, T=0, ws=None, wsb=0) == 0
+    assert j2(L, n0=2, ws=None, wsb=0) == 0
+    assert j2(L, n1=1, ws=None, wsb=0) == 0
+
+
+def test_jacobi_plan(L):
+    assert L.jacobi_plan(1, 24000, 1, 1000) == (32, 64)      # 999 iterations, 32 passes of 31-32
+    assert L.jacobi_plan(1, 24000 * 1296, 1, 1000) == (16, 126)
+    assert L.jacobi_plan(2, 1300, 1300, 1000) == (168, 12)
+    assert L.jacobi_plan(2, 1300, 1300, 1000, 1) == (1998, 1)
+    assert L.jacobi_plan(2, 1300, 1300, 2, 8) == (2, 1)      # one iteration: split at the half-step
+    assert L.jacobi_plan(1, 2, 1, 50) == (0, 0)
+    assert L.jacobi_plan(2, 50, 50, 1) == (0, 0)
+    for dims, n0, n1, T, tb in ((1, 5000, 1, 77, 5), (2, 300, 200, 33, 7), (1, 10, 1, 3, 256)):
+        P, hh = L.jacobi_plan(dims, n0, n1, T, tb)
+        assert P % 2 == 0 and 1 <= hh <= tb
+        assert P * hh >= 2 * (T - 1)
+    n = ctypes.c_int64(0)
+    h = ctypes.c_int32(0)
+    assert L.lib().dcp_jacobi_plan(2, 10, 1 << 30, 5, 0, ctypes.byref(n), ctypes.byref(h)) == -2
+    assert L.lib().dcp_jacobi_plan(2, 10, 10, 5, 0, None, ctypes.byref(h)) == -1

@@ -1,0 +1,222 @@
+"""GPU parity of the Jacobi programs (jacobi_1d, Sec. 2.2; jacobi_2d,
+Sec. 4.3) against the oracle.
+
+The listings add their terms in a fixed order and scale once, and both sides
+round every operation once, so the bar is bit-for-bit equality of A and B
+for every size, step count and tblock (half-steps per pass).  The cases span
+one and many tiles, ragged tails, arrays with no interior, TSTEPS <= 1,
+every pass split the planner makes (odd and even pass sizes, both phases),
+the paper's problem sizes at T=1000, and the weak-scaled sizes at 1296
+processes on sampled windows that the oracle evaluates one by one."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import DEV, say, to_dev, to_host
+from paper_2107_00555_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _api():
+    from paper_2107_00555_amd import api
+    return api
+
+
+def gpu_run(dims, tsteps, A, B, tblock=0):
+    api = _api()
+    a, b = to_dev(A), to_dev(B)
+    (api.jacobi_1d if dims == 1 else api.jacobi_2d)(a, b, tsteps, tblock)
+    torch.cuda.synchronize()
+    return to_host(a), to_host(b)
+
+
+def assert_same(got, want, what):
+    for g, w, name in ((got[0], want[0], "A"), (got[1], want[1], "B")):
+        if not np.array_equal(g, w):
+            bad = np.argwhere(g != w)
+            raise AssertionError(f"{what}: {name} differs at {len(bad)} cells, first {bad[:3].tolist()}, "
+                                 f"max |diff| {np.max(np.abs(g - w))}")
+
+
+CASES_1D = [(n, t, tb) for n in (3, 4, 63, 64, 65, 1023, 1025, 5000)
+            for t in (0, 1, 2, 3, 17) for tb in (0, 1, 3)]
+CASES_1D += [(24000, 60, tb) for tb in (2, 5, 64, 255, 256)]
+CASES_1D += [(10000, 300, 256), (70000, 41, 7), (1 << 16, 9, 16)]
+
+
+@pytest.mark.parametrize("n,tsteps,tblock", CASES_1D)
+def test_jacobi_1d_matches_oracle_bitwise(n, tsteps, tblock):
+    A, B = inputs.jacobi_fields(1, n, seed=n + tsteps)
+    say(f"jacobi_1d n={n} tsteps={tsteps} tblock={tblock}")
+    assert_same(gpu_run(1, tsteps, A, B, tblock), oracle.jacobi_1d(tsteps, A, B), "jacobi_1d")
+
+
+SHAPES_2D = [(3, 3), (3, 200), (200, 3), (4, 5), (47, 113), (64, 128), (65, 129), (130, 250), (257, 511)]
+CASES_2D = [(s, t, tb) for s in SHAPES_2D for t in (2, 3, 9) for tb in (0, 1, 5)]
+CASES_2D += [((100, 300), 30, tb) for tb in (2, 3, 8, 15, 16)]
+CASES_2D += [((1, 40), 5, 0), ((40, 2), 5, 0), ((0, 0), 5, 0), ((33, 47), 0, 0), ((33, 47), 1, 4)]
+
+
+@pytest.mark.parametrize("shape,tsteps,tblock", CASES_2D)
+def test_jacobi_2d_matches_oracle_bitwise(shape, tsteps, tblock):
+    A, B = inputs.jacobi_fields(2, shape[0], seed=shape[0] * 7 + shape[1], n1=shape[1])
+    say(f"jacobi_2d shape={shape} tsteps={tsteps} tblock={tblock}")
+    assert_same(gpu_run(2, tsteps, A, B, tblock), oracle.jacobi_2d(tsteps, A, B), "jacobi_2d")
+
+
+@pytest.mark.parametrize("k", [4, 8, 16, 32])
+@pytest.mark.parametrize("n,tsteps,tblock", [(5000, 40, 20), (70001, 13, 64), (3, 9, 1), (2049, 30, 7)])
+def test_jacobi_1d_every_run_length(monkeypatch, k, n, tsteps, tblock):
+    """Each compiled points-per-lane variant, forced through the tuning knob
+    (the library ignores it when the halo does not fit)."""
+    monkeypatch.setenv("DCP_J1_K", str(k))
+    A, B = inputs.jacobi_fields(1, n, seed=k + n)
+    say(f"jacobi_1d K={k} n={n} tsteps={tsteps} tblock={tblock}")
+    assert_same(gpu_run(1, tsteps, A, B, tblock), oracle.jacobi_1d(tsteps, A, B), f"jacobi_1d K={k}")
+
+
+@pytest.mark.parametrize("cfg", [0, 1])
+@pytest.mark.parametrize("shape,tsteps,tblock", [((300, 200), 9, 12), ((150, 130), 9, 16), ((3, 400), 6, 3),
+                                                  ((257, 511), 14, 5), ((1300, 1300), 20, 0), ((140, 129), 2, 1)])
+def test_jacobi_2d_every_workgroup_shape(monkeypatch, cfg, shape, tsteps, tblock):
+    """Each compiled workgroup shape, forced through the tuning knob."""
+    monkeypatch.setenv("DCP_J2_CFG", str(cfg))
+    A, B = inputs.jacobi_fields(2, shape[0], seed=cfg + shape[0], n1=shape[1])
+    say(f"jacobi_2d cfg={cfg} shape={shape} tsteps={tsteps} tblock={tblock}")
+    assert_same(gpu_run(2, tsteps, A, B, tblock), oracle.jacobi_2d(tsteps, A, B), f"jacobi_2d cfg={cfg}")
+
+
+@pytest.mark.parametrize("tblock", [0, 1, 256])
+def test_jacobi_1d_paper_size_full_run(tblock):
+    w = inputs.JACOBI_WORKLOADS["jacobi_1d_paper"]
+    A, B = inputs.jacobi_fields(1, w["n"], seed=0)
+    say(f"jacobi_1d paper size n={w['n']} tsteps={w['tsteps']} tblock={tblock}")
+    assert_same(gpu_run(1, w["tsteps"], A, B, tblock), oracle.jacobi_1d(w["tsteps"], A, B), "jacobi_1d")
+
+
+@pytest.fixture(scope="module")
+def oracle_2d_paper():
+    w = inputs.JACOBI_WORKLOADS["jacobi_2d_paper"]
+    A, B = inputs.jacobi_fields(2, w["n"], seed=0)
+    return A, B, oracle.jacobi_2d(w["tsteps"], A, B)
+
+
+@pytest.mark.parametrize("tblock,cfg", [(0, ""), (1, ""), (16, ""), (12, "1")])
+def test_jacobi_2d_paper_size_full_run(monkeypatch, oracle_2d_paper, tblock, cfg):
+    monkeypatch.setenv("DCP_J2_CFG", cfg)
+    A, B, want = oracle_2d_paper
+    T = inputs.JACOBI_WORKLOADS["jacobi_2d_paper"]["tsteps"]
+    say(f"jacobi_2d paper size n={A.shape[0]} tsteps={T} tblock={tblock}")
+    assert_same(gpu_run(2, T, A, B, tblock), want, "jacobi_2d")
+
+
+def test_jacobi_on_a_side_stream_with_reused_workspace():
+    api = _api()
+    A, B = inputs.jacobi_fields(2, 150, seed=5, n1=170)
+    want = oracle.jacobi_2d(12, A, B)
+    a, b = to_dev(A), to_dev(B)
+    ws = torch.empty(1 << 20, dtype=torch.uint8, device=DEV)
+    s = torch.cuda.Stream(device=DEV)
+    s.wait_stream(torch.cuda.current_stream(DEV))
+    say("jacobi_2d on a side stream")
+    with torch.cuda.stream(s):
+        api.jacobi_2d(a, b, 12, 0, ws=ws)
+    s.synchronize()
+    assert_same((to_host(a), to_host(b)), want, "side stream")
+    A1, B1 = inputs.jacobi_fields(1, 3000, seed=6)
+    a1, b1 = to_dev(A1), to_dev(B1)
+    api.jacobi_1d(a1, b1, 40, 0, ws=ws)
+    torch.cuda.synchronize()
+    assert_same((to_host(a1), to_host(b1)), oracle.jacobi_1d(40, A1, B1), "reused workspace")
+
+
+def test_jacobi_rejects_bad_tensors():
+    api = _api()
+    a = torch.zeros(10, dtype=torch.float64, device=DEV)
+    with pytest.raises(ValueError):
+        api.jacobi_1d(a, a[:9], 3)
+    with pytest.raises(TypeError):
+        api.jacobi_1d(a.float(), a.float(), 3)
+    with pytest.raises(api.DcpError):
+        api.jacobi_1d(a, a, 3)          # A and B are the same memory
+    with pytest.raises(api.DcpError):
+        api.jacobi_2d(a.view(2, 5), a.clone().view(2, 5), 3, tblock=17)
+
+
+# ---------------------------------------------------- weak-scaled full sizes
+def _windows_1d(n, H, width):
+    return [(0, width + H), (n // 2 - width // 2 - H, width + 2 * H), (n - width - H, width + H)]
+
+
+def test_jacobi_1d_p1296_full_run_sampled():
+    """n = 24000*1296, T = 1000 on the device-drawn inputs; the oracle runs
+    the same program on windows wide enough that 64 cells stay exact."""
+    w = inputs.JACOBI_WORKLOADS["jacobi_1d_p1296"]
+    n, T = w["n"], w["tsteps"]
+    H = 2 * (T - 1)
+    a, b = inputs.jacobi_fields_device(1, n, seed=0, device=DEV)
+    wins = _windows_1d(n, H, 64)
+    ins = [(to_host(a[c0:c0 + L]), to_host(b[c0:c0 + L])) for c0, L in wins]
+    say(f"jacobi_1d n={n} tsteps={T}")
+    _api().jacobi_1d(a, b, T)
+    torch.cuda.synchronize()
+    for (c0, L), (wa, wb) in zip(wins, ins):
+        ra, rb = oracle.jacobi_1d_box(T, n, c0, wa, wb)
+        lo = 0 if c0 == 0 else H
+        hi = L if c0 + L == n else L - H
+        got = (to_host(a[c0 + lo:c0 + hi]), to_host(b[c0 + lo:c0 + hi]))
+        assert_same(got, (ra[lo:hi], rb[lo:hi]), f"window at {c0}")
+    assert torch.isfinite(a).all() and torch.isfinite(b).all()
+
+
+def _check_2d_windows(a, b, wins_in, T, n, after):
+    H = 2 * (T - 1)
+    for (r0, c0, h0, h1), (wa, wb) in zip(after, wins_in):
+        ra, rb = oracle.jacobi_2d_box(T, n, n, r0, c0, wa, wb)
+        lo0 = 0 if r0 == 0 else H
+        hi0 = h0 if r0 + h0 == n else h0 - H
+        lo1 = 0 if c0 == 0 else H
+        hi1 = h1 if c0 + h1 == n else h1 - H
+        got = (to_host(a[r0 + lo0:r0 + hi0, c0 + lo1:c0 + hi1]),
+               to_host(b[r0 + lo0:r0 + hi0, c0 + lo1:c0 + hi1]))
+        assert_same(got, (ra[lo0:hi0, lo1:hi1], rb[lo0:hi0, lo1:hi1]), f"window at {(r0, c0)}")
+
+
+@pytest.fixture(scope="module")
+def fields_2d_p1296():
+    w = inputs.JACOBI_WORKLOADS["jacobi_2d_p1296"]
+    return w["n"], inputs.jacobi_fields_device(2, w["n"], seed=0, device=DEV)
+
+
+def test_jacobi_2d_p1296_short_run_sampled_windows(fields_2d_p1296):
+    """N = 1300*36 at T = 12 (22 half-steps): corners, edges and interior."""
+    n, (a0, b0) = fields_2d_p1296
+    T = 12
+    H = 2 * (T - 1)
+    s = 40 + 2 * H
+    wins = [(0, 0, s, s), (0, n // 3, s, s), (n - s, n - s, s, s), (n // 2, 777, s, s),
+            (n - s, 5000, s, s), (12345, n - s, s, s)]
+    a, b = a0.clone(), b0.clone()
+    ins = [(to_host(a[r:r + h0, c:c + h1]), to_host(b[r:r + h0, c:c + h1])) for r, c, h0, h1 in wins]
+    say(f"jacobi_2d n={n} tsteps={T}")
+    _api().jacobi_2d(a, b, T)
+    torch.cuda.synchronize()
+    _check_2d_windows(a, b, ins, T, n, wins)
+
+
+def test_jacobi_2d_p1296_full_run_corner_window(fields_2d_p1296):
+    """N = 1300*36 at the workload's T = 1000; the oracle evaluates the
+    corner window that 48 x 48 exact cells depend on."""
+    n, (a, b) = fields_2d_p1296
+    T = inputs.JACOBI_WORKLOADS["jacobi_2d_p1296"]["tsteps"]
+    H = 2 * (T - 1)
+    s = 48 + H
+    wins = [(0, 0, s, s)]
+    ins = [(to_host(a[:s, :s]), to_host(b[:s, :s]))]
+    say(f"jacobi_2d n={n} tsteps={T}")
+    _api().jacobi_2d(a, b, T)
+    torch.cuda.synchronize()
+    _check_2d_windows(a, b, ins, T, n, wins)
+    assert torch.isfinite(a).all() and torch.isfinite(b).all()
