@@ -54,8 +54,14 @@ def parse():
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--seed", type=int, default=0)
-    p.add_argument("--forms", choices=["main", "all"], default="all")
+    p.add_argument("--forms", choices=["main", "all", "jacobi"], default="all",
+                   help="main: the headline only; all: every form; jacobi: the Jacobi forms only "
+                        "(no headline line; for profiling)")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--jacobi-workloads", default="all",
+                   help="comma-separated Jacobi workloads to time (names in inputs.JACOBI_WORKLOADS)")
+    p.add_argument("--jacobi-no-compare", action="store_true",
+                   help="skip the one-half-step-per-pass comparison runs of the Jacobi forms")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="also run a plain 1 GiB device copy (counter calibration)")
     p.add_argument("--tblock", type=int, default=2,
@@ -131,6 +137,66 @@ def cpu_baseline(u0, f, coeffs, bc):
                       f"steps on the full 512^3 periodic grid, {dt:.1f} s"}
 
 
+def jacobi_forms(args, dev, stream) -> dict:
+    """The two Jacobi listings at the paper's sizes and weak-scaled to 1296
+    processes: event-timed runs of the library's default schedule, the pass
+    schedule, per-pass HBM traffic and useful FP64 rate, and (small sizes)
+    the speedup over one half-step per pass."""
+    import torch
+
+    from paper_2107_00555_amd import _lib, api, inputs
+    jac = {}
+    pick = None if args.jacobi_workloads == "all" else set(args.jacobi_workloads.split(","))
+    if pick is not None and not pick <= set(inputs.JACOBI_WORKLOADS):
+        raise SystemExit(f"unknown Jacobi workload in {sorted(pick)}")
+    if args.calibrate_copy:
+        # the library's own copy kernel, 1 GiB read + 1 GiB write (counter
+        # calibration): a one-step dcp_run with a checkpoint every step
+        # copies u into slot 0 first
+        uc = torch.rand(512, 512, 512, dtype=torch.float64, device=dev)
+        api.run(uc, torch.zeros_like(uc), dict(inputs.BASE_COEFFS), 1, inputs.PERIODIC, norms=False,
+                ckpt_every=1)
+        torch.cuda.synchronize()
+        del uc
+    for name, w in inputs.JACOBI_WORKLOADS.items():
+        if pick is not None and name not in pick:
+            continue
+        dims, n, Tj = w["dims"], w["n"], w["tsteps"]
+        n1 = n if dims == 2 else 1
+        a, b = inputs.jacobi_fields_device(dims, n, seed=args.seed, device=dev)
+        wsj = api.workspace(_lib.jacobi_workspace_bytes(dims, n, n1, Tj, 0), dev)
+        run_j = api.jacobi_1d if dims == 1 else api.jacobi_2d
+        N = a.numel()
+        lups = (n - 2) ** dims * 2 * (Tj - 1)   # interior points x half-steps
+        flops = 3 if dims == 1 else 5           # adds and one multiply per update
+        big = N > (1 << 26)
+        kj = max(1, min(args.steps, 3 if big else 10))
+        log(f"timing {name} (n={n}, T={Tj})")
+        # each call continues from the arrays the previous one left
+        ms_j, per_j, _ = timed(lambda: run_j(a, b, Tj, 0, ws=wsj), kj, max(0, min(args.warmup, 1)), stream)
+        ms_j /= kj
+        passes, halo = _lib.jacobi_plan(dims, n, n1, Tj, 0)
+        pass_ms = ms_j / passes
+        gbs = 16 * N / (pass_ms * 1e-3) / 1e9
+        tfl = lups * flops / (ms_j * 1e-3) / 1e12
+        ent = {"dims": dims, "n": n, "tsteps": Tj, "passes": passes, "halfsteps_per_pass": halo,
+               "ms": round(ms_j, 4), "ms_median_ci95": [round(x, 4) for x in bootstrap_ci(per_j)],
+               "glups": round(lups / (ms_j * 1e-3) / 1e9, 2),
+               # a pass reads A and writes A (16 B per element); the last also writes B
+               "hbm_per_pass": {"bytes": 16 * N, "gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)},
+               "alu_useful": {"tflops": round(tfl, 3), "peak": FP64_NONFMA_PEAK_TFLOPS,
+                              "frac": round(tfl / FP64_NONFMA_PEAK_TFLOPS, 4)}}
+        if not big and not args.jacobi_no_compare:
+            ms_1, _, _ = timed(lambda: run_j(a, b, Tj, 1, ws=wsj), 3, 1, stream)
+            ms_1 /= 3
+            ent["ms_one_halfstep_per_pass"] = round(ms_1, 3)
+            ent["speedup_over_one_halfstep_per_pass"] = round(ms_1 / ms_j, 2)
+        jac[name] = ent
+        del a, b, wsj
+        torch.cuda.empty_cache()
+    return jac
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -145,6 +211,9 @@ def main():
 
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
+    if args.forms == "jacobi":
+        print(json.dumps({"forms": {"jacobi": jacobi_forms(args, dev, stream)}, "data": "synthetic"}), flush=True)
+        return
     nx = ny = nz = 512
     N = nx * ny * nz
     T = 100
@@ -328,42 +397,7 @@ def main():
     # ------------------------------------------------ the Jacobi listings
     if args.forms == "all":
         torch.cuda.empty_cache()
-        jac = {}
-        out["forms"]["jacobi"] = jac
-        for name, w in inputs.JACOBI_WORKLOADS.items():
-            dims, n, Tj = w["dims"], w["n"], w["tsteps"]
-            n1 = n if dims == 2 else 1
-            a, b = inputs.jacobi_fields_device(dims, n, seed=args.seed, device=dev)
-            wsj = api.workspace(_lib.jacobi_workspace_bytes(dims, n, n1, Tj, 0), dev)
-            run_j = api.jacobi_1d if dims == 1 else api.jacobi_2d
-            N = a.numel()
-            lups = (n - 2) ** dims * 2 * (Tj - 1)   # interior points x half-steps
-            flops = 3 if dims == 1 else 5           # adds and one multiply per update
-            big = N > (1 << 26)
-            kj = 3 if big else max(5, kk)
-            log(f"timing {name} (n={n}, T={Tj})")
-            # each call continues from the arrays the previous one left
-            ms_j, per_j, _ = timed(lambda: run_j(a, b, Tj, 0, ws=wsj), kj, 1, stream)
-            ms_j /= kj
-            passes, halo = _lib.jacobi_plan(dims, n, n1, Tj, 0)
-            pass_ms = ms_j / passes
-            ent = {"dims": dims, "n": n, "tsteps": Tj, "passes": passes, "halfsteps_per_pass": halo,
-                   "ms": round(ms_j, 4), "ms_median_ci95": [round(x, 4) for x in bootstrap_ci(per_j)],
-                   "glups": round(lups / (ms_j * 1e-3) / 1e9, 2),
-                   # a pass reads A and writes A (16 B per element); the last also writes B
-                   "hbm_per_pass": {"bytes": 16 * N, "gbs": round(16 * N / (pass_ms * 1e-3) / 1e9, 1),
-                                    "frac": round(16 * N / (pass_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
-                   "alu_useful": {"tflops": round(lups * flops / (ms_j * 1e-3) / 1e12, 3),
-                                  "peak": FP64_NONFMA_PEAK_TFLOPS,
-                                  "frac": round(lups * flops / (ms_j * 1e-3) / 1e12 / FP64_NONFMA_PEAK_TFLOPS, 4)}}
-            if not big:
-                ms_1, _, _ = timed(lambda: run_j(a, b, Tj, 1, ws=wsj), 3, 1, stream)
-                ms_1 /= 3
-                ent["ms_one_halfstep_per_pass"] = round(ms_1, 3)
-                ent["speedup_over_one_halfstep_per_pass"] = round(ms_1 / ms_j, 2)
-            jac[name] = ent
-            del a, b, wsj
-            torch.cuda.empty_cache()
+        out["forms"]["jacobi"] = jacobi_forms(args, dev, stream)
 
     # --------------------------------------------------------- CPU oracle
     if not args.no_cpu_baseline:

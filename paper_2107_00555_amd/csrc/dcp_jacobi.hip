@@ -22,6 +22,7 @@
 // ends in the caller's arrays.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstdlib>
 #include <type_traits>
@@ -45,13 +46,60 @@ struct J1Args {
     int write_b;
 };
 
+// vec16: every lane's two columns are one aligned 16-byte pair (n1 and hh
+// even, arrays 16-byte aligned), so loads and stores move both at once.
+// set: which tiles this launch covers: 0 = all, 1 = the interior rectangle
+// [r_lo, r_hi] x [c_lo, c_hi] of tiles whose region holds no boundary cell of
+// the array, 2 = the ring of the other tiles (see j2_tile).
 struct J2Args {
     const double *ain, *bin, *bfix;
     double *aout, *bout;
     int64_t n0, n1;
-    int inner_r, inner_c, tiles_c;
-    int hh, nhalf, phase, write_b;
+    int inner_r, inner_c, tiles_r, tiles_c;
+    int hh, nhalf, phase, write_b, vec16;
+    int set, r_lo, r_hi, c_lo, c_hi;
 };
+
+// Tile (row, column) of workgroup b (after the XCD renumbering).  Tiles run
+// column by column, so a tile's upper and lower neighbours (whose halos it
+// shares, the larger overlap) are recent in the same XCD's L2.
+__device__ __forceinline__ void j2_tile(const J2Args &a, int b, int &tr, int &tc) {
+    if (a.set == 0) {
+        tr = b % a.tiles_r;
+        tc = b / a.tiles_r;
+        return;
+    }
+    if (a.set == 1) {
+        const int nr = a.r_hi - a.r_lo + 1;
+        tr = a.r_lo + b % nr;
+        tc = a.c_lo + b / nr;
+        return;
+    }
+    // ring: the rows above and below the rectangle in full, then the columns
+    // left and right of it on the rectangle's rows
+    const int top = a.r_lo * a.tiles_c, below = (a.tiles_r - 1 - a.r_hi) * a.tiles_c;
+    if (b < top) {
+        tr = b / a.tiles_c;
+        tc = b % a.tiles_c;
+        return;
+    }
+    b -= top;
+    if (b < below) {
+        tr = a.r_hi + 1 + b / a.tiles_c;
+        tc = b % a.tiles_c;
+        return;
+    }
+    b -= below;
+    const int nr = a.r_hi - a.r_lo + 1, left = a.c_lo, right = a.tiles_c - 1 - a.c_hi;
+    if (b < nr * left) {
+        tr = a.r_lo + b / left;
+        tc = b % left;
+        return;
+    }
+    b -= nr * left;
+    tr = a.r_lo + b / right;
+    tc = a.c_hi + 1 + b % right;
+}
 
 __device__ __forceinline__ int j_xcd_remap(int b, int nb) {
     // consecutive workgroups go to different XCDs; number the tiles so that
@@ -203,7 +251,10 @@ __global__ void __launch_bounds__(64) j1_kernel(J1Args a) {
 // east neighbours across lanes come from DPP shifts, the rows above and below
 // a wave's band from the neighbouring waves through LDS (two slots, so one
 // barrier per half-step suffices).
-template <int W, int RPL, int MINW>
+// MASK = false: every cell is updated; only for tiles whose region holds no
+// boundary cell of the array.  MASK = true: boundary cells keep their values;
+// any tile.  (One kernel with both paths needs more registers than either.)
+template <int W, int RPL, int MINW, bool MASK>
 __global__ void __launch_bounds__(64 * W, MINW) j2_kernel(J2Args a) {
     constexpr int VEC = 2;
     constexpr int R = W * RPL, C = 64 * VEC;
@@ -211,8 +262,8 @@ __global__ void __launch_bounds__(64 * W, MINW) j2_kernel(J2Args a) {
     // the wave index is uniform over a wave: say so, so that everything that
     // depends only on the row (bounds, masks, row addresses) stays scalar
     const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int b = j_xcd_remap(blockIdx.x, gridDim.x);
-    const int tr = b / a.tiles_c, tc = b % a.tiles_c;
+    int tr, tc;
+    j2_tile(a, j_xcd_remap(blockIdx.x, gridDim.x), tr, tc);
     const int64_t n0 = a.n0;
     const int n1 = (int)a.n1;  // < 2^30, checked by the host
     const int ri0 = wave * RPL;
@@ -234,11 +285,6 @@ __global__ void __launch_bounds__(64 * W, MINW) j2_kernel(J2Args a) {
         if (j >= 0 && j < n1) colin |= 1u << v;
         colfix[v] = __builtin_amdgcn_ballot_w64(j == 0 || j == n1 - 1);
     }
-    // the region holds no boundary cell of the array (uniform over the workgroup)
-    const int64_t rr0 = (int64_t)tr * a.inner_r - a.hh;
-    const int cc0 = tc * a.inner_c - a.hh;
-    const bool edge = rr0 <= 0 || rr0 + R - 1 >= n0 - 1 || cc0 <= 0 || cc0 + C - 1 >= n1 - 1;
-
     double va[RPL][VEC], vb[RPL][VEC];
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
@@ -246,18 +292,41 @@ __global__ void __launch_bounds__(64 * W, MINW) j2_kernel(J2Args a) {
         const double *rowa = a.ain + i * n1;
         const double *rowb = (a.phase ? a.bin : a.bfix) + i * n1;
         const bool rfix = (rowfix >> r) & 1u;
+        if (a.vec16) {
+            // both columns are in the array or neither (gc even, n1 even)
+            const bool in = ((rowin >> r) & 1u) && (colin & 1u);
+            const double2 x = in ? *reinterpret_cast<const double2 *>(rowa + (unsigned)gc) : double2{0.0, 0.0};
+            va[r][0] = x.x;
+            va[r][1] = x.y;
+        }
 #pragma unroll
         for (int v = 0; v < VEC; ++v) {
             const bool in = ((rowin >> r) & 1u) && ((colin >> v) & 1u);
             const unsigned j = (unsigned)(gc + v);
             const bool fixed = rfix || j == 0 || j == (unsigned)(n1 - 1);
-            va[r][v] = in ? rowa[j] : 0.0;
+            if (!a.vec16) va[r][v] = in ? rowa[j] : 0.0;
             vb[r][v] = (in && (a.phase || fixed)) ? rowb[j] : 0.0;
         }
     }
 
+    // Edge tiles: the values a half-step must keep.  Boundary rows are kept
+    // whole (skipped, a uniform branch); on other rows a lane holds at most
+    // one boundary-column cell (the array's first or last column, n1 >= 3
+    // when anything is updated), whose A and B values never change, so they
+    // are captured once here instead of keeping every old value alive.
+    double fixa[RPL], fixb[RPL];
+    if constexpr (MASK) {
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const bool v1 = (colfix[1] >> lane) & 1ull;
+            fixa[r] = v1 ? va[r][1] : va[r][0];
+            fixb[r] = v1 ? vb[r][1] : vb[r][0];
+        }
+    }
+
     int slot = 0;
-    auto half = [&](double(&d)[RPL][VEC], const double(&s)[RPL][VEC], auto masked) __attribute__((always_inline)) {
+    auto half = [&](double(&d)[RPL][VEC], const double(&s)[RPL][VEC], const double(&fix)[RPL],
+                    auto masked) __attribute__((always_inline)) {
 #pragma unroll
         for (int v = 0; v < VEC; ++v) {
             xch[slot][wave][0][lane * VEC + v] = s[0][v];
@@ -289,7 +358,7 @@ __global__ void __launch_bounds__(64 * W, MINW) j2_kernel(J2Args a) {
                 if constexpr (decltype(masked)::value) {
                     // a boundary row keeps all its cells (uniform branch), other
                     // rows keep the lanes on a boundary column
-                    if (!((rowfix >> r) & 1u)) d[r][v] = j_keep(colfix[v], nv, d[r][v]);
+                    if (!((rowfix >> r) & 1u)) d[r][v] = j_keep(colfix[v], nv, fix[r]);
                 } else {
                     d[r][v] = nv;
                 }
@@ -299,17 +368,16 @@ __global__ void __launch_bounds__(64 * W, MINW) j2_kernel(J2Args a) {
     auto steps = [&](auto masked) __attribute__((always_inline)) {
         int s = 0;
         if (a.phase && a.nhalf > 0) {
-            half(va, vb, masked);
+            half(va, vb, fixa, masked);
             s = 1;
         }
         for (; s + 2 <= a.nhalf; s += 2) {
-            half(vb, va, masked);
-            half(va, vb, masked);
+            half(vb, va, fixb, masked);
+            half(va, vb, fixa, masked);
         }
-        if (s < a.nhalf) half(vb, va, masked);
+        if (s < a.nhalf) half(vb, va, fixb, masked);
     };
-    if (edge) steps(std::true_type{});
-    else steps(std::false_type{});
+    steps(std::integral_constant<bool, MASK>{});
 
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
@@ -319,13 +387,19 @@ __global__ void __launch_bounds__(64 * W, MINW) j2_kernel(J2Args a) {
         double *rowa = a.aout + i * n1;
         double *rowb = a.bout + i * n1;
         const bool binterior_row = i >= 1 && i <= n0 - 2;
+        // with vec16 both columns are inside the tile or neither (hh even)
+        if (a.vec16 && lane * VEC >= a.hh && lane * VEC < C - a.hh && (colin & 1u)) {
+            *reinterpret_cast<double2 *>(rowa + (unsigned)gc) = double2{va[r][0], va[r][1]};
+            if (a.write_b == 1) *reinterpret_cast<double2 *>(rowb + (unsigned)gc) = double2{vb[r][0], vb[r][1]};
+        }
 #pragma unroll
         for (int v = 0; v < VEC; ++v) {
             const int ci = lane * VEC + v;
             if (ci < a.hh || ci >= C - a.hh || !((colin >> v) & 1u)) continue;
             const unsigned j = (unsigned)(gc + v);
-            rowa[j] = va[r][v];
-            if (a.write_b == 1 || (a.write_b == 2 && binterior_row && j >= 1 && j <= (unsigned)(n1 - 2)))
+            if (!a.vec16) rowa[j] = va[r][v];
+            if ((a.write_b == 1 && !a.vec16) ||
+                (a.write_b == 2 && binterior_row && j >= 1 && j <= (unsigned)(n1 - 2)))
                 rowb[j] = vb[r][v];
         }
     }
@@ -354,24 +428,53 @@ int j1_pick_k(int64_t n, int64_t hh) {
     return 32;
 }
 
-// 2D workgroup shapes: (waves, rows per lane); eight rows per lane keep a
-// lane's state (two arrays, 8 x 2 cells) within the 128 VGPRs that four waves
-// per SIMD allow.  The 8-wave shape (64 x 128 regions) measured fastest at
-// both 1300^2 and 46800^2 (the 16-wave one, 128-row regions with less halo,
-// and a 4-wave 16-rows-per-lane one at two waves per SIMD were slower);
-// DCP_J2_CFG=1 forces the 16-wave shape (tuning runs only).
+// 2D workgroup shapes: (waves, rows per lane), all within the 128 VGPRs of
+// four waves per SIMD without spilling (a kernel holding both the masked and
+// the unmasked update spilled about 64 bytes per lane, which at 46800^2
+// wrote about 15 GB per pass to HBM; hence one instantiation per path).
 struct J2Cfg {
     int w, rpl;
 };
-constexpr J2Cfg kJ2Cfgs[] = {{8, 8}, {16, 8}};
+constexpr J2Cfg kJ2Cfgs[] = {{16, 4}, {8, 8}, {16, 8}};
 
-int j2_pick_cfg(int64_t hh) {
-    const char *forced = std::getenv("DCP_J2_CFG");
-    if (forced && *forced) {
-        const int c = std::atoi(forced);
-        if (c >= 0 && c < 2 && kJ2Cfgs[c].w * kJ2Cfgs[c].rpl > 2 * hh) return c;
+// Launch plan of a 2D pass: a shape and whether the pass is split into the
+// ring of edge tiles (masked) and the interior rectangle (unmasked, two
+// launches) or run as one masked launch.  Measured at T=1000: large arrays
+// (46800^2: 1834 vs 1554 GLUP/s) gain from the split with 16 x 4; small ones
+// (1300^2, a fifth of the tiles in the ring, launch-bound) run best as one
+// launch of 8 x 8.  DCP_J2_CFG / DCP_J2_MODE (1 = one launch, 2 = split)
+// force the choice (tuning runs only).
+struct J2Plan {
+    int cfg;
+    bool split;
+};
+
+int64_t j2_interior_tiles(int64_t n0, int64_t n1, int64_t hh, int rows, int64_t *all) {
+    const int64_t ir = rows - 2 * hh, ic = 128 - 2 * hh;
+    const int64_t tr = (n0 + ir - 1) / ir, tc = (n1 + ic - 1) / ic;
+    *all = tr * tc;
+    auto span = [&](int64_t n, int64_t inner, int extent, int64_t tiles) {
+        const int64_t lo = (hh + 1 + inner - 1) / inner;
+        const int64_t num = n - 2 - (extent - 1) + hh;
+        const int64_t hi = num < 0 ? -1 : std::min<int64_t>(num / inner, tiles - 1);
+        return hi >= lo ? hi - lo + 1 : 0;
+    };
+    return span(n0, ir, rows, tr) * span(n1, ic, 128, tc);
+}
+
+J2Plan j2_pick(int64_t n0, int64_t n1, int64_t hh) {
+    J2Plan p{1, false};
+    int64_t all = 0;
+    const int64_t in = j2_interior_tiles(n0, n1, hh, kJ2Cfgs[0].w * kJ2Cfgs[0].rpl, &all);
+    if (all >= 2048 && in * 10 >= all * 9) p = J2Plan{0, true};
+    const char *fc = std::getenv("DCP_J2_CFG");
+    if (fc && *fc) {
+        const int c = std::atoi(fc);
+        if (c >= 0 && c < 3 && kJ2Cfgs[c].w * kJ2Cfgs[c].rpl > 2 * hh) p.cfg = c;
     }
-    return 0;
+    const char *fm = std::getenv("DCP_J2_MODE");
+    if (fm && *fm) p.split = std::atoi(fm) == 2;
+    return p;
 }
 
 template <int K>
@@ -575,24 +678,64 @@ int dcp_jacobi_2d(int32_t tsteps, double *A, double *B, int64_t n0, int64_t n1, 
     const JPlan p = j_plan(g, tsteps, hp);
     st = j_check_buffers(g, A, B, ws, ws_bytes, j_ws_need(g, p));
     if (st != DCP_OK || p.passes == 0) return st;
-    const int cfg = j2_pick_cfg(p.hh);
+    const J2Plan plan = j2_pick(n0, n1, p.hh);
+    const int cfg = plan.cfg;
     const int rows = kJ2Cfgs[cfg].w * kJ2Cfgs[cfg].rpl;
     const int inner_r = rows - 2 * (int)p.hh, inner_c = kJ2C - 2 * (int)p.hh;
     const int64_t tiles_r = (n0 + inner_r - 1) / inner_r, tiles_c = (n1 + inner_c - 1) / inner_c;
     if (tiles_c > INT32_MAX || tiles_r > INT32_MAX / tiles_c) return DCP_E_SHAPE;
-    const int64_t blocks = tiles_r * tiles_c;
+    // interior rectangle: tiles whose region [t*inner - hh, t*inner - hh + extent)
+    // lies in [1, n - 2] on both axes
+    auto lo_hi = [&](int64_t n, int inner, int extent, int64_t tiles, int &lo, int &hi) {
+        lo = (int)((p.hh + 1 + inner - 1) / inner);
+        const int64_t num = n - 2 - (extent - 1) + p.hh;
+        hi = num < 0 ? -1 : (int)std::min<int64_t>(num / inner, tiles - 1);
+    };
+    int r_lo, r_hi, c_lo, c_hi;
+    lo_hi(n0, inner_r, rows, tiles_r, r_lo, r_hi);
+    lo_hi(n1, inner_c, kJ2C, tiles_c, c_lo, c_hi);
+    if (r_lo > r_hi || c_lo > c_hi) {  // no interior tile: everything is ring
+        r_lo = (int)tiles_r;
+        r_hi = (int)tiles_r - 1;
+        c_lo = 0;
+        c_hi = -1;
+    }
+    const int64_t n_in = (int64_t)(r_hi - r_lo + 1) * (c_hi >= c_lo ? c_hi - c_lo + 1 : 0);
+    const int64_t n_all = tiles_r * tiles_c, n_ring = n_all - n_in;
+    // one masked launch over all tiles, or the ring (masked) and the interior
+    // rectangle (unmasked) as two launches
+    const bool split = plan.split && n_in > 0;
     hipStream_t sm = static_cast<hipStream_t>(stream);
+    auto launch_set = [&](J2Args a, int set, int64_t blocks, bool mask) -> hipError_t {
+        a.set = set;
+        const dim3 grid((unsigned)blocks);
+        if (cfg == 1) {
+            if (mask) hipLaunchKernelGGL((j2_kernel<8, 8, 4, true>), grid, dim3(512), 0, sm, a);
+            else hipLaunchKernelGGL((j2_kernel<8, 8, 4, false>), grid, dim3(512), 0, sm, a);
+        } else if (cfg == 2) {
+            if (mask) hipLaunchKernelGGL((j2_kernel<16, 8, 4, true>), grid, dim3(1024), 0, sm, a);
+            else hipLaunchKernelGGL((j2_kernel<16, 8, 4, false>), grid, dim3(1024), 0, sm, a);
+        } else {
+            if (mask) hipLaunchKernelGGL((j2_kernel<16, 4, 4, true>), grid, dim3(1024), 0, sm, a);
+            else hipLaunchKernelGGL((j2_kernel<16, 4, 4, false>), grid, dim3(1024), 0, sm, a);
+        }
+        return hipGetLastError();
+    };
     return j_run_passes(g, p, A, B, ws,
                         [&](const double *ain, const double *bin, const double *bfix, double *aout, double *bout,
                             int nh, int ph, int wb) {
-                            const J2Args a{ain, bin, bfix, aout, bout, n0, n1, inner_r, inner_c, (int)tiles_c,
-                                           (int)p.hh, nh, ph, wb};
-                            const dim3 grid((unsigned)blocks);
-                            if (cfg == 1)
-                                hipLaunchKernelGGL((j2_kernel<16, 8, 4>), grid, dim3(1024), 0, sm, a);
-                            else
-                                hipLaunchKernelGGL((j2_kernel<8, 8, 4>), grid, dim3(512), 0, sm, a);
-                            return hipGetLastError();
+                            const bool v16 = (n1 % 2 == 0) && (p.hh % 2 == 0) &&
+                                             ((uintptr_t)ain | (uintptr_t)bin | (uintptr_t)bfix |
+                                              (uintptr_t)aout | (uintptr_t)bout) % 16 == 0;
+                            const J2Args a{ain, bin, bfix, aout, bout, n0, n1, inner_r, inner_c,
+                                           (int)tiles_r, (int)tiles_c, (int)p.hh, nh, ph, wb, v16 ? 1 : 0,
+                                           0, r_lo, r_hi, c_lo, c_hi};
+                            if (!split) return launch_set(a, 0, n_all, true);
+                            if (n_ring > 0) {
+                                const hipError_t e = launch_set(a, 2, n_ring, true);
+                                if (e != hipSuccess) return e;
+                            }
+                            return launch_set(a, 1, n_in, false);
                         });
 }
 

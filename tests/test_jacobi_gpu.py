@@ -77,15 +77,20 @@ def test_jacobi_1d_every_run_length(monkeypatch, k, n, tsteps, tblock):
     assert_same(gpu_run(1, tsteps, A, B, tblock), oracle.jacobi_1d(tsteps, A, B), f"jacobi_1d K={k}")
 
 
-@pytest.mark.parametrize("cfg", [0, 1])
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("cfg", [0, 1, 2])
 @pytest.mark.parametrize("shape,tsteps,tblock", [((300, 200), 9, 12), ((150, 130), 9, 16), ((3, 400), 6, 3),
-                                                  ((257, 511), 14, 5), ((1300, 1300), 20, 0), ((140, 129), 2, 1)])
-def test_jacobi_2d_every_workgroup_shape(monkeypatch, cfg, shape, tsteps, tblock):
-    """Each compiled workgroup shape, forced through the tuning knob."""
+                                                  ((257, 511), 14, 5), ((1300, 1300), 20, 0), ((140, 129), 2, 1),
+                                                  ((700, 900), 7, 8)])
+def test_jacobi_2d_every_workgroup_shape(monkeypatch, mode, cfg, shape, tsteps, tblock):
+    """Each compiled workgroup shape and both launch modes (one masked launch
+    over all tiles; the ring of edge tiles masked plus the interior tiles
+    unmasked), forced through the tuning knobs."""
     monkeypatch.setenv("DCP_J2_CFG", str(cfg))
+    monkeypatch.setenv("DCP_J2_MODE", str(mode))
     A, B = inputs.jacobi_fields(2, shape[0], seed=cfg + shape[0], n1=shape[1])
-    say(f"jacobi_2d cfg={cfg} shape={shape} tsteps={tsteps} tblock={tblock}")
-    assert_same(gpu_run(2, tsteps, A, B, tblock), oracle.jacobi_2d(tsteps, A, B), f"jacobi_2d cfg={cfg}")
+    say(f"jacobi_2d cfg={cfg} mode={mode} shape={shape} tsteps={tsteps} tblock={tblock}")
+    assert_same(gpu_run(2, tsteps, A, B, tblock), oracle.jacobi_2d(tsteps, A, B), f"jacobi_2d cfg={cfg} mode={mode}")
 
 
 @pytest.mark.parametrize("tblock", [0, 1, 256])
@@ -103,7 +108,7 @@ def oracle_2d_paper():
     return A, B, oracle.jacobi_2d(w["tsteps"], A, B)
 
 
-@pytest.mark.parametrize("tblock,cfg", [(0, ""), (1, ""), (16, ""), (12, "1")])
+@pytest.mark.parametrize("tblock,cfg", [(0, ""), (1, ""), (16, ""), (12, "1"), (12, "2")])
 def test_jacobi_2d_paper_size_full_run(monkeypatch, oracle_2d_paper, tblock, cfg):
     monkeypatch.setenv("DCP_J2_CFG", cfg)
     A, B, want = oracle_2d_paper
