@@ -58,7 +58,7 @@ def _load():
                                        ctypes.c_int, ctypes.c_int, i64p, i64p, dp]
         lib.oracle_run_box.restype = ctypes.c_int
         lib.oracle_adjoint.argtypes = [i64, i64, i64, dp, dp, dp, d, d, d, d, d,
-                                       ctypes.c_int, ctypes.c_int, dp, dp]
+                                       ctypes.c_int, ctypes.c_int, dp, dp, dp, dp]
         lib.oracle_adjoint.restype = ctypes.c_int
         lib.oracle_half_sq_dist.argtypes = [i64, dp, dp]
         lib.oracle_half_sq_dist.restype = d
@@ -132,17 +132,27 @@ def adjoint(u0, f, lam_T, coeffs: dict, T: int, bc: int):
 
     Returns ``(dL/du0, dL/dalpha, dL/dbeta)``.
     """
+    r = adjoint_full(u0, f, lam_T, coeffs, T, bc)
+    return r["u0"], r["alpha"], r["beta"]
+
+
+def adjoint_full(u0, f, lam_T, coeffs: dict, T: int, bc: int) -> dict:
+    """Every gradient through T steps given lam_T = dL/du_T: a dict with
+    'u0', 'f' (fields) and 'alpha', 'beta', 'gamma' (floats)."""
     u0 = _field(u0)
     f = _field(f)
     lam_T = _field(lam_T)
     nz, ny, nx = u0.shape
     g = np.empty_like(u0)
+    gf = np.empty_like(u0)
     gab = np.empty(2, dtype=np.float64)
+    gg = np.empty(1, dtype=np.float64)
     rc = _load().oracle_adjoint(nx, ny, nz, _ptr(u0), _ptr(f), _ptr(lam_T),
-                                *_coeffs(coeffs), int(bc), int(T), _ptr(g), _ptr(gab))
+                                *_coeffs(coeffs), int(bc), int(T), _ptr(g), _ptr(gab),
+                                _ptr(gf), _ptr(gg))
     if rc != 0:
         raise ValueError(f"oracle_adjoint failed with code {rc}")
-    return g, float(gab[0]), float(gab[1])
+    return {"u0": g, "f": gf, "alpha": float(gab[0]), "beta": float(gab[1]), "gamma": float(gg[0])}
 
 
 def half_sq_dist(a, b) -> float:

@@ -29,6 +29,10 @@
  *         lambda_t = J_t^T lambda_{t+1}
  *         dL/dalpha = sum_t dt * <lambda_{t+1}, L u_t>
  *         dL/dbeta  = sum_t -dt * <lambda_{t+1}, u_t^3>
+ *         dL/dgamma = sum_t dt * <lambda_{t+1}, f>
+ *         dL/df     = gamma * dt * sum_t lambda_{t+1}
+ *     (u_{t+1} depends on gamma through dt*gamma*f and on f through
+ *     dt*gamma*f, the same at every step)
  *     L^T is applied by a literal scatter (each point sends its value to the
  *     points that read it), so the oracle does not assume L is symmetric.
  *
@@ -330,10 +334,12 @@ int oracle_run_box(int64_t nx, int64_t ny, int64_t nz, const double *u0,
  *   gB     += -dt * sum lambda_{t+1} * u_t^3
  *   lambda_t = lambda_{t+1} + dt*(alpha*LT - 3*beta*u_t^2*lambda_{t+1})
  */
+/* grad_f (N doubles) and grad_gamma (one double) are optional (NULL). */
 int oracle_adjoint(int64_t nx, int64_t ny, int64_t nz, const double *u0,
                    const double *f, const double *lamT, double alpha,
                    double beta, double gamma, double h, double dt, int bc,
-                   int T, double *grad_u0, double *grad_ab) {
+                   int T, double *grad_u0, double *grad_ab, double *grad_f,
+                   double *grad_gamma) {
     int rc = check_common(nx, ny, nz, bc, T, h);
     if (rc) return rc;
     grid_t g = {{nx, ny, nz}, {bc, bc, bc}};
@@ -361,7 +367,10 @@ int oracle_adjoint(int64_t nx, int64_t ny, int64_t nz, const double *u0,
 
     double *lcur = lam[0], *lnext = lam[1], *lt = lam[2];
     if (n > 0) memcpy(lcur, lamT, (size_t)n * sizeof(double));
-    nsum_t ga = {0, 0}, gb = {0, 0};
+    nsum_t ga = {0, 0}, gb = {0, 0}, gg = {0, 0};
+    /* sum of the lambda_{t+1} seen so far, per point (accumulated in grad_f) */
+    if (grad_f)
+        for (int64_t p = 0; p < n; ++p) grad_f[p] = 0.0;
     const double inv_h2 = 1.0 / (h * h);
     for (int t = T - 1; t >= 0; --t) {
         const double *u = states[t];
@@ -395,6 +404,13 @@ int oracle_adjoint(int64_t nx, int64_t ny, int64_t nz, const double *u0,
                 }
         nsum_add(&ga, dt * nsum_value(&sa));
         nsum_add(&gb, -dt * nsum_value(&sb));
+        if (grad_gamma) {
+            nsum_t sg = {0, 0};
+            for (int64_t p = 0; p < n; ++p) nsum_add(&sg, lcur[p] * f[p]);
+            nsum_add(&gg, dt * nsum_value(&sg));
+        }
+        if (grad_f)
+            for (int64_t p = 0; p < n; ++p) grad_f[p] += lcur[p];
         for (int64_t p = 0; p < n; ++p)
             lnext[p] = lcur[p] + dt * (alpha * lt[p] - 3.0 * beta * (u[p] * u[p]) * lcur[p]);
         double *sw = lcur;
@@ -404,6 +420,9 @@ int oracle_adjoint(int64_t nx, int64_t ny, int64_t nz, const double *u0,
     if (n > 0) memcpy(grad_u0, lcur, (size_t)n * sizeof(double));
     grad_ab[0] = nsum_value(&ga);
     grad_ab[1] = nsum_value(&gb);
+    if (grad_gamma) *grad_gamma = nsum_value(&gg);
+    if (grad_f)
+        for (int64_t p = 0; p < n; ++p) grad_f[p] = (gamma * dt) * grad_f[p];
     free_fields(states, nst);
     free(states);
     free_fields(tmp, T_COUNT);

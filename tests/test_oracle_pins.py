@@ -283,3 +283,74 @@ def test_adjoint_zero_steps():
     w = np.random.default_rng(19).uniform(-1, 1, u.shape)
     g, ga, gb = oracle.adjoint(u, f, w, BASE, 0, 1)
     assert np.array_equal(g, w) and ga == 0.0 and gb == 0.0
+
+
+# ------------------------------------------ gradients in gamma and f (NEXT-4)
+def _grad_full(u0, f, tgt, c, T, bc):
+    uT, _, _ = oracle.run(u0, f, c, T, bc, norms=False)
+    return oracle.adjoint_full(u0, f, uT - tgt, c, T, bc), uT
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_gamma_f_gradients_closed_form_without_stencil_and_reaction(bc):
+    # alpha = beta = 0: J_t = I, so lambda_t = lambda_T for every t and
+    # u_T = u_0 + T dt gamma f:  dL/df = gamma dt T lambda_T,
+    # dL/dgamma = dt T <lambda_T, f>, dL/du0 = lambda_T.
+    u0, f = _rand((5, 4, 3), 30)
+    tgt = np.random.default_rng(31).uniform(-1, 1, u0.shape)
+    c = dict(alpha=0.0, beta=0.0, gamma=0.7, h=1.0, dt=0.1)
+    T = 6
+    r, uT = _grad_full(u0, f, tgt, c, T, bc)
+    lam = uT - tgt
+    assert np.max(np.abs(r["f"] - c["gamma"] * c["dt"] * T * lam)) <= 1e-14
+    assert r["gamma"] == pytest.approx(c["dt"] * T * np.sum(lam * f), rel=1e-13)
+    assert np.max(np.abs(r["u0"] - lam)) <= 1e-15
+
+
+def test_gamma_f_gradients_closed_form_periodic_cosine():
+    # beta = 0, u_tgt = 0, u0 = A cos(th), f = B cos(th), th = 2 pi m x / nx:
+    # u_t = c_t cos(th) with c_{t+1} = r c_t + dt gamma B, so
+    # c_T = r^T A + dt gamma B S_T, S_T = sum_{k<T} r^k, L = c_T^2 N/4,
+    # dL/dgamma = c_T dt B S_T N/2, lambda_{t+1} = r^(T-1-t) c_T cos(th),
+    # dL/df = gamma dt c_T S_T cos(th).
+    nx, ny, nz, m, A, B, T = 12, 3, 4, 1, 0.6, -0.4, 9
+    c = dict(alpha=1.0, beta=0.0, gamma=0.5, h=1.0, dt=0.1)
+    x = np.arange(nx)
+    cos = np.broadcast_to(np.cos(2 * np.pi * m * x / nx), (nz, ny, nx)).copy()
+    N = nx * ny * nz
+    r = 1 + c["dt"] * c["alpha"] * (2 * np.cos(2 * np.pi * m / nx) - 2)
+    S = np.sum(r ** np.arange(T))
+    cT = r ** T * A + c["dt"] * c["gamma"] * B * S
+    out, _ = _grad_full(A * cos, B * cos, np.zeros_like(cos), c, T, 1)
+    assert out["gamma"] == pytest.approx(cT * c["dt"] * B * S * N / 2, rel=1e-13)
+    assert np.max(np.abs(out["f"] - c["gamma"] * c["dt"] * cT * S * cos)) <= 1e-14
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_gamma_f_gradients_match_central_differences(bc):
+    shape = (5, 4, 3)
+    u, f = _rand(shape, 32)
+    tgt = np.random.default_rng(33).uniform(-1, 1, u.shape)
+    T, eps = 4, 1e-6
+    r, _ = _grad_full(u, f, tgt, BASE, T, bc)
+
+    def L(df=0.0, dg=0.0):
+        cc = dict(BASE, gamma=BASE["gamma"] + dg)
+        uT, _, _ = oracle.run(u, f + df, cc, T, bc, norms=False)
+        return oracle.half_sq_dist(uT, tgt)
+
+    rng = np.random.default_rng(34)
+    for _ in range(4):
+        df = rng.uniform(-1, 1, u.shape)
+        dg = rng.normal()
+        fd = (L(eps * df, eps * dg) - L(-eps * df, -eps * dg)) / (2 * eps)
+        an = np.sum(r["f"] * df) + r["gamma"] * dg
+        assert abs(fd - an) <= 1e-6 * abs(an)
+    assert (L(dg=eps) - L(dg=-eps)) / (2 * eps) == pytest.approx(r["gamma"], rel=1e-6)
+
+
+def test_gamma_f_gradients_zero_steps():
+    u, f = _rand((3, 4, 2), 35)
+    w = np.random.default_rng(36).uniform(-1, 1, u.shape)
+    r = oracle.adjoint_full(u, f, w, BASE, 0, 1)
+    assert r["gamma"] == 0.0 and np.all(r["f"] == 0.0)
