@@ -372,6 +372,14 @@ def main():
             ms_a /= kk
             forms[f"adjoint_{name}"] = {"glups": round(glups(ms_a, Ta), 3), "ms_per_step": round(ms_a / Ta, 4),
                                         "hbm_frac": round(frac(ms_a, 3 * S, Ta), 4)}
+            # the same steps also accumulating the sum of the adjoint inputs
+            # (dL/df, dL/dgamma): one more read and write of a field per pass
+            log(f"timing adjoint kernel {name} with dL/df and dL/dgamma")
+            ms_al, _, _ = timed(lambda: api.adjoint_run(ck, 1, ff, lam, coeffs, Ta, bc, ws=wsa, grad_u0=g,
+                                                        want_f=True, want_gamma=True), kk, 1, stream)
+            ms_al /= kk
+            forms[f"adjoint_{name}_with_f_gamma"] = {"glups": round(glups(ms_al, Ta), 3),
+                                                     "ms_per_step": round(ms_al / Ta, 4)}
             del ck, wsa, g, lam, ua
 
         # end-to-end gradient, float64: forward T=100 with checkpoints every 10, then adjoint
@@ -392,6 +400,17 @@ def main():
         ms_g /= kk
         forms["gradient_f64_T100_k10"] = {"ms": round(ms_g, 3),
                                           "ms_over_forward": round(ms_g / ms_step, 3)}
+
+        def grad_step_all():
+            ug.copy_(u0)
+            api.run(ug, f64, coeffs, T, bc, tblock=args.tblock, norms=False, ckpt_every=kck, ws=wsf, ckpt=ck)
+            api.adjoint_run(ck, kck, f64, ug, coeffs, T, bc, ws=wsa, grad_u0=g, want_f=True, want_gamma=True)
+
+        log("timing end-to-end gradient f64 with dL/df and dL/dgamma")
+        ms_ga, _, _ = timed(grad_step_all, kk, 1, stream)
+        ms_ga /= kk
+        forms["gradient_f64_T100_k10_all_inputs"] = {"ms": round(ms_ga, 3),
+                                                     "ms_over_forward": round(ms_ga / ms_step, 3)}
         del ck, wsf, wsa, g, ug, u32, f32
 
     # ------------------------------------------------ the Jacobi listings

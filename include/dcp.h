@@ -105,7 +105,9 @@ typedef struct {
  *   ckpt_every  checkpoint interval k (DCP_OP_ADJOINT: >= 1; ignored otherwise)
  *   tblock      steps per pass over memory (DCP_OP_RUN fused, DCP_OP_ADJOINT;
  *               1 = one step per pass)
- *   norms       nonzero if the call will request norms (energy/resid/norms2)
+ *   norms       nonzero if the call will request norms (energy/resid/norms2);
+ *               for DCP_OP_ADJOINT: nonzero if it will request grad_gamma
+ *               without grad_f (one more field of workspace)
  * The size is an upper bound valid for any pointer alignment.  Writes it to
  * *bytes (a host pointer).  Returns DCP_OK or an argument error.
  */
@@ -177,6 +179,8 @@ int dcp_run(int dtype, int impl, void *u, const void *f, int64_t nx,
  *     lambda_t = J_t^T lambda_{t+1}                    (t = T-1 .. 0)
  *     dL/dalpha = sum_t dt * <lambda_{t+1}, L u_t>
  *     dL/dbeta  = sum_t -dt * <lambda_{t+1}, u_t^3>
+ *     dL/dgamma = sum_t dt * <lambda_{t+1}, f>        (optional)
+ *     dL/df     = gamma * dt * sum_t lambda_{t+1}     (optional)
  * Segments [c*k, min(T, c*k+k)) are processed last to first: the states
  * inside a segment are recomputed from its checkpoint with the forward
  * kernel, then one fused adjoint kernel per step applies J_t^T (L is
@@ -194,11 +198,21 @@ int dcp_run(int dtype, int impl, void *u, const void *f, int64_t nx,
  *   grad_ab [2] out, double: {dL/dalpha, dL/dbeta}, reduced in a fixed order,
  *               so for a given tblock the result does not depend on k bit
  *               for bit (dL/du_0 does not depend on tblock either)
+ *   grad_f  [N] out, optional (NULL: not computed): dL/df.  The adjoint
+ *               kernels add each step's input lambda_{t+1} into it, in step
+ *               order (t = T-1 .. 0) and in the field's type; it is then
+ *               scaled by gamma*dt.  Does not depend on k or tblock, bit for
+ *               bit.  Must not overlap any other argument.
+ *   grad_gamma [1] out, double, optional: dL/dgamma = dt * <sum of the
+ *               lambda_{t+1}, f>, a fixed-order double reduction.  Without
+ *               grad_f the running sum lives in the workspace (size it with
+ *               norms = 1).
  */
 int dcp_adjoint_run(int dtype, const void *ckpt, int32_t ckpt_every,
                     const void *f, const void *lam_T, int64_t nx, int64_t ny,
                     int64_t nz, const dcp_coeffs *coeffs, int bc, int32_t T,
-                    int32_t tblock, void *grad_u0, double *grad_ab, void *ws,
+                    int32_t tblock, void *grad_u0, double *grad_ab,
+                    void *grad_f, double *grad_gamma, void *ws,
                     size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------

@@ -70,7 +70,7 @@ def lib() -> ctypes.CDLL:
                           vp, sz, vp]
     L.dcp_run.restype = c_int
     L.dcp_adjoint_run.argtypes = [c_int, vp, i32, vp, vp, i64, i64, i64, cp, c_int, i32, i32, vp, dp,
-                                  vp, sz, vp]
+                                  vp, dp, vp, sz, vp]
     L.dcp_adjoint_run.restype = c_int
     L.dcp_status_string.argtypes = [c_int]
     L.dcp_status_string.restype = ctypes.c_char_p

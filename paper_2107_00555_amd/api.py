@@ -130,9 +130,10 @@ def run(u: torch.Tensor, f: torch.Tensor, coeffs, T: int, bc, impl="fused", tblo
 
 def adjoint_run(ckpt: torch.Tensor | None, ckpt_every: int, f: torch.Tensor, lam_T: torch.Tensor,
                 coeffs, T: int, bc, tblock: int = 2, ws: torch.Tensor | None = None,
-                grad_u0: torch.Tensor | None = None):
+                grad_u0: torch.Tensor | None = None, want_f: bool = False, want_gamma: bool = False):
     """Gradient through T fused steps from dcp_run's checkpoints.
-    Returns (dL/du0, float64 tensor [dL/dalpha, dL/dbeta])."""
+    Returns (dL/du0, float64 tensor [dL/dalpha, dL/dbeta]), or with
+    want_f / want_gamma a dict with keys 'u0', 'ab', and 'f' / 'gamma'."""
     lam_T = _field("lam_T", lam_T)
     f = _field("f", f, lam_T)
     dt = _dtype_code(lam_T)
@@ -142,17 +143,27 @@ def adjoint_run(ckpt: torch.Tensor | None, ckpt_every: int, f: torch.Tensor, lam
                 or ckpt.numel() < num_slots(T, ckpt_every) * lam_T.numel():
             raise ValueError("ckpt must hold ceil(T/ckpt_every) contiguous fields of the state dtype")
     c = Coeffs.make(coeffs)
-    wsb = _lib.workspace_bytes(OP_ADJOINT, dt, nx, ny, nz, T=T, ckpt_every=ckpt_every, tblock=tblock)
+    wsb = _lib.workspace_bytes(OP_ADJOINT, dt, nx, ny, nz, T=T, ckpt_every=ckpt_every, tblock=tblock,
+                               norms=want_gamma and not want_f)
     if ws is None or ws.numel() < wsb:
         ws = workspace(wsb, lam_T.device)
     if grad_u0 is None:
         grad_u0 = torch.empty_like(lam_T)
     gab = torch.empty(2, dtype=torch.float64, device=lam_T.device)
+    gf = torch.empty_like(lam_T) if want_f else None
+    gg = torch.empty(1, dtype=torch.float64, device=lam_T.device) if want_gamma else None
     _lib.check("dcp_adjoint_run", _lib.lib().dcp_adjoint_run(
         dt, _ptr(ckpt), int(ckpt_every), _ptr(f), _ptr(lam_T), nx, ny, nz, ctypes.byref(c),
-        bc_code(bc), int(T), int(tblock), _ptr(grad_u0), _ptr(gab), _ptr(ws), wsb, _stream(lam_T.device)))
-    return grad_u0, gab
-
+        bc_code(bc), int(T), int(tblock), _ptr(grad_u0), _ptr(gab), _ptr(gf), _ptr(gg), _ptr(ws), wsb,
+        _stream(lam_T.device)))
+    if not (want_f or want_gamma):
+        return grad_u0, gab
+    out = {"u0": grad_u0, "ab": gab}
+    if want_f:
+        out["f"] = gf
+    if want_gamma:
+        out["gamma"] = gg[0]
+    return out
 
 def _jacobi_arrays(A: torch.Tensor, B: torch.Tensor, dims: int):
     for name, t in (("A", A), ("B", B)):

@@ -3,7 +3,8 @@
 forward runs dcp_run with checkpoints every k steps; backward runs
 dcp_adjoint_run, which recomputes each segment from its checkpoint and
 applies the hand-written adjoint kernel.  Gradients are returned for u0,
-alpha and beta; gamma, f, dt, h, T, the boundary and k get None.
+f, alpha, beta and gamma (the scalars when passed as tensors); dt, h, T,
+the boundary and k get None.
 """
 from __future__ import annotations
 
@@ -14,6 +15,15 @@ from . import api
 
 def _scalar(x) -> float:
     return float(x.detach().item()) if isinstance(x, torch.Tensor) else float(x)
+
+
+def _meta(x):
+    return (x.dtype, x.device, x.shape) if isinstance(x, torch.Tensor) else None
+
+
+def _as(meta, v: torch.Tensor) -> torch.Tensor:
+    dtype, device, shape = meta
+    return v.to(dtype=dtype, device=device).reshape(shape)
 
 
 class RD3D(torch.autograd.Function):
@@ -30,27 +40,27 @@ class RD3D(torch.autograd.Function):
         ctx.T, ctx.bc, ctx.k = int(T), bc, k
         ctx.ckpt = out["ckpt"]
         ctx.f = f.detach().contiguous()
-        ctx.alpha_is_tensor = isinstance(alpha, torch.Tensor)
-        ctx.beta_is_tensor = isinstance(beta, torch.Tensor)
-        ctx.alpha_meta = (alpha.dtype, alpha.device, alpha.shape) if ctx.alpha_is_tensor else None
-        ctx.beta_meta = (beta.dtype, beta.device, beta.shape) if ctx.beta_is_tensor else None
+        ctx.metas = (_meta(alpha), _meta(beta), _meta(gamma))
         return u
 
     @staticmethod
     def backward(ctx, grad_uT):
-        g, gab = api.adjoint_run(ctx.ckpt, ctx.k, ctx.f, grad_uT.contiguous(), ctx.coeffs,
-                                 ctx.T, ctx.bc, tblock=ctx.tblock)
-        ga = gb = None
-        if ctx.needs_input_grad[2] and ctx.alpha_is_tensor:
-            dtype, device, shape = ctx.alpha_meta
-            ga = gab[0].to(dtype=dtype, device=device).reshape(shape)
-        if ctx.needs_input_grad[3] and ctx.beta_is_tensor:
-            dtype, device, shape = ctx.beta_meta
-            gb = gab[1].to(dtype=dtype, device=device).reshape(shape)
-        gu = g if ctx.needs_input_grad[0] else None
-        return gu, None, ga, gb, None, None, None, None, None, None, None
+        ma, mb, mg = ctx.metas
+        want_f = ctx.needs_input_grad[1]
+        want_gamma = ctx.needs_input_grad[4] and mg is not None
+        r = api.adjoint_run(ctx.ckpt, ctx.k, ctx.f, grad_uT.contiguous(), ctx.coeffs, ctx.T, ctx.bc,
+                            tblock=ctx.tblock, want_f=want_f, want_gamma=want_gamma)
+        if not isinstance(r, dict):
+            r = {"u0": r[0], "ab": r[1]}
+        gu = r["u0"] if ctx.needs_input_grad[0] else None
+        gf = r["f"] if want_f else None
+        ga = _as(ma, r["ab"][0]) if ctx.needs_input_grad[2] and ma is not None else None
+        gb = _as(mb, r["ab"][1]) if ctx.needs_input_grad[3] and mb is not None else None
+        gg = _as(mg, r["gamma"]) if want_gamma else None
+        return gu, gf, ga, gb, gg, None, None, None, None, None, None
 
 
 def rd3d(u0, f, alpha, beta, gamma, dt, h, T, bc, ckpt_every=10, tblock=2):
-    """u_T after T fused steps from u0, differentiable in u0, alpha and beta."""
+    """u_T after T fused steps from u0, differentiable in u0, f, alpha, beta
+    and gamma."""
     return RD3D.apply(u0, f, alpha, beta, gamma, dt, h, T, bc, ckpt_every, tblock)

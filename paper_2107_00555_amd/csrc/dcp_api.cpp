@@ -183,11 +183,14 @@ struct AdjWs {
     size_t seg = 0;       // k-1 fields
     size_t partials = 0;  // [T][nblk][2]
     size_t sums = 0;      // [T][2]
+    size_t lsum = 0;      // 1 field: running sum of the adjoint inputs (when wanted there)
+    size_t dot = 0;       // [ew_norm_blocks][2] + 2: partials of <sum, f>
     int nblk = 0;
     size_t total = 0;
 };
 
-int layout_adj(int dtype, const Geo &g, int32_t T, int32_t k, int32_t tblock, AdjWs *w) {
+// lsum_field: reserve the running-sum field (dL/dgamma without a grad_f buffer).
+int layout_adj(int dtype, const Geo &g, int32_t T, int32_t k, int32_t tblock, bool lsum_field, AdjWs *w) {
     size_t off = 0;
     if (T == 0) {
         w->total = 0;
@@ -206,6 +209,12 @@ int layout_adj(int dtype, const Geo &g, int32_t T, int32_t k, int32_t tblock, Ad
         off += (size_t)(kk - 1) * align_up(g.bytes());
         w->partials = off;
         off += align_up((size_t)T * nb * 2 * sizeof(double));
+        if (lsum_field) {
+            w->lsum = off;
+            off += align_up(g.bytes());
+        }
+        w->dot = off;
+        off += align_up(((size_t)ew_norm_blocks(g.n) * 2 + 2) * sizeof(double));
     }
     w->sums = off;
     off += align_up((size_t)T * 2 * sizeof(double));
@@ -419,7 +428,7 @@ int dcp_workspace_bytes(int op, int dtype, int impl, int64_t nx, int64_t ny, int
             if (T < 0 || ckpt_every < 1) return DCP_E_ARG;
             if (tblock < 1 || tblock > dcp_max_tblock(dtype)) return DCP_E_ARG;
             AdjWs w;
-            if ((rc = layout_adj(dtype, g, T, ckpt_every, tblock, &w))) return rc;
+            if ((rc = layout_adj(dtype, g, T, ckpt_every, tblock, norms != 0, &w))) return rc;
             *bytes = w.total;
             return DCP_OK;
         }
@@ -535,7 +544,8 @@ int dcp_run(int dtype, int impl, void *u, const void *f, int64_t nx, int64_t ny,
 
 int dcp_adjoint_run(int dtype, const void *ckpt, int32_t ckpt_every, const void *f, const void *lam_T, int64_t nx,
                     int64_t ny, int64_t nz, const dcp_coeffs *coeffs, int bc, int32_t T, int32_t tblock,
-                    void *grad_u0, double *grad_ab, void *ws, size_t ws_bytes, void *stream) {
+                    void *grad_u0, double *grad_ab, void *grad_f, double *grad_gamma, void *ws, size_t ws_bytes,
+                    void *stream) {
     Geo g;
     int rc = check_geo(dtype, nx, ny, nz, &g);
     if (rc) return rc;
@@ -544,8 +554,9 @@ int dcp_adjoint_run(int dtype, const void *ckpt, int32_t ckpt_every, const void 
     if (T < 0 || ckpt_every < 1 || tblock < 1 || tblock > dcp_max_tblock(dtype)) return DCP_E_ARG;
     if (!grad_ab) return DCP_E_NULL;
     if (g.n > 0 && (!f || !lam_T || !grad_u0 || (T > 0 && !ckpt))) return DCP_E_NULL;
+    const bool lsum_field = grad_gamma != nullptr && grad_f == nullptr && g.n > 0;
     AdjWs w;
-    if ((rc = layout_adj(dtype, g, T, ckpt_every, tblock, &w))) return rc;
+    if ((rc = layout_adj(dtype, g, T, ckpt_every, tblock, lsum_field, &w))) return rc;
     if ((rc = check_ws(ws, ws_bytes, w.total))) return rc;
     const size_t fb = g.bytes();
     const int32_t nslots = num_slots(T, ckpt_every);
@@ -557,21 +568,35 @@ int dcp_adjoint_run(int dtype, const void *ckpt, int32_t ckpt_every, const void 
         return DCP_E_ALIAS;
     if (overlaps(grad_ab, 16, grad_u0, fb) || overlaps(grad_ab, 16, ws, w.total) || overlaps(grad_ab, 16, ckpt, cb))
         return DCP_E_ALIAS;
+    if (grad_f && (overlaps(grad_f, fb, ckpt, cb) || overlaps(grad_f, fb, f, fb) || overlaps(grad_f, fb, lam_T, fb) ||
+                   overlaps(grad_f, fb, grad_u0, fb) || overlaps(grad_f, fb, ws, w.total) ||
+                   overlaps(grad_f, fb, grad_ab, 16)))
+        return DCP_E_ALIAS;
+    if (grad_gamma && (overlaps(grad_gamma, 8, grad_ab, 16) || overlaps(grad_gamma, 8, grad_u0, fb) ||
+                       overlaps(grad_gamma, 8, grad_f, grad_f ? fb : 0) || overlaps(grad_gamma, 8, ws, w.total) ||
+                       overlaps(grad_gamma, 8, ckpt, cb)))
+        return DCP_E_ALIAS;
 
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (T == 0 || g.n == 0) {
         if (g.n > 0)
             DCP_TRY(launch_ew(dtype, EW_COPY, lam_T, nullptr, grad_u0, 0.0, g.n,
                               vec_ok_for(dtype, g, {lam_T, grad_u0}), st));
+        if (grad_f && g.n > 0)
+            DCP_TRY(launch_ew(dtype, EW_ZERO, nullptr, nullptr, grad_f, 0.0, g.n, vec_ok_for(dtype, g, {grad_f}), st));
         DCP_TRY(launch_zero(grad_ab, 2, st));
+        if (grad_gamma) DCP_TRY(launch_zero(grad_gamma, 1, st));
         return DCP_OK;
     }
+    // running sum of the adjoint inputs lambda_T .. lambda_1 (for dL/df and dL/dgamma)
+    void *lsum = grad_f ? grad_f : (lsum_field ? static_cast<void *>(at(ws, w.lsum)) : nullptr);
 
     void *lam[2] = {at(ws, w.lam), at(ws, w.lam + align_up(fb))};
     const int32_t kk = ckpt_every < T ? ckpt_every : T;
     auto seg = [&](int32_t j) { return static_cast<void *>(at(ws, w.seg + (size_t)j * align_up(fb))); };
     auto slot = [&](int32_t c) { return static_cast<const void *>(static_cast<const char *>(ckpt) + (size_t)c * fb); };
     bool vok = vec_ok_for(dtype, g, {f, lam_T, grad_u0, lam[0], lam[1]});
+    if (lsum) vok = vok && aligned16(lsum);
     for (int32_t c = 0; c < nslots; ++c) vok = vok && aligned16(slot(c));
     for (int32_t j = 0; j + 1 < kk; ++j) vok = vok && aligned16(seg(j));
     const Tile t = pick_tile(dtype, g, vok);
@@ -607,6 +632,10 @@ int dcp_adjoint_run(int dtype, const void *ckpt, int32_t ckpt_every, const void 
     // Every step's parameter sums therefore come from the same kernel with the
     // same tiling for any k, and the gradient does not depend on k bit for bit.
     std::vector<int> step_nblk((size_t)T, t.nblk);
+    const int adj_op = lsum ? SOP_ADJL : SOP_ADJ;
+    aa.lam = lsum;
+    ta.lam = lsum;
+    int lam_first = 1;
     const void *lcur = lam_T;
     int32_t s = T - 1;  // next adjoint step to take
     for (int32_t cs = nslots - 1; cs >= 0; --cs) {
@@ -643,15 +672,18 @@ int dcp_adjoint_run(int dtype, const void *ckpt, int32_t ckpt_every, const void 
                 ta.mid = nullptr;
                 ta.part1 = partials + (size_t)s * stride * 2;
                 ta.part2 = partials + (size_t)(s - 1) * stride * 2;
-                DCP_TRY(launch_tb2(dtype, SOP_ADJ, bc, true, tb, ta, st));
+                ta.lam_first = lam_first;
+                DCP_TRY(launch_tb2(dtype, adj_op, bc, true, tb, ta, st));
                 step_nblk[s] = step_nblk[s - 1] = tb.nblk;
             } else {
                 aa.s = lcur;
                 aa.q = state(s);
                 aa.out = out;
                 aa.partials = partials + (size_t)s * stride * 2;
-                DCP_TRY(launch_stencil(dtype, SOP_ADJ, bc, true, t, aa, st));
+                aa.lam_first = lam_first;
+                DCP_TRY(launch_stencil(dtype, adj_op, bc, true, t, aa, st));
             }
+            lam_first = 0;
             lcur = out;
             s = se - 1;
         }
@@ -665,6 +697,21 @@ int dcp_adjoint_run(int dtype, const void *ckpt, int32_t ckpt_every, const void 
         s0 = s1;
     }
     DCP_TRY(launch_grad_finalize(sums, T, c.dt / (c.h * c.h), -c.dt, grad_ab, st));
+    if (lsum) {
+        // dL/dgamma = dt * <sum, f> (fixed-order double reduction), then
+        // dL/df = gamma * dt * sum in place
+        if (grad_gamma) {
+            double *dp = reinterpret_cast<double *>(at(ws, w.dot));
+            const int nb = ew_norm_blocks(g.n);
+            double *pair = dp + 2 * (size_t)nb;
+            DCP_TRY(launch_ew_dot(dtype, lsum, f, dp, g.n, vec_ok_for(dtype, g, {lsum, f}), st));
+            DCP_TRY(launch_finalize(dp, nb, nb, 1, pair, nullptr, 0, st));
+            DCP_TRY(launch_scalar_scale(pair, c.dt, grad_gamma, st));
+        }
+        if (grad_f)
+            DCP_TRY(launch_ew(dtype, EW_SCALE, grad_f, nullptr, grad_f, c.gamma * c.dt, g.n,
+                              vec_ok_for(dtype, g, {grad_f}), st));
+    }
     return DCP_OK;
 }
 

@@ -12,6 +12,8 @@ enum StencilOp : int {
     SOP_FWD = 0,  // u' = u + c0*(S6 - 6u) - c1*u^3 + c2*f      (S6 = sum of 6 neighbours)
     SOP_ADJ = 1,  // l' = l + c0*(S6 - 6l) - c1*u^2*l ; sums (S6-6l)*u and l*u^3
     SOP_LAP = 2,  // lap = (((((xm+xp)+ym)+yp)+zm)+zp - 6u) / c0, one rounding per op
+    SOP_ADJL = 3, // SOP_ADJ, and lam += l (the adjoint step's input, lambda_{t+1});
+                  // lam_first: lam = l + 0 without reading lam
 };
 
 // Tile of one workgroup: 64*bxw*vec points along x (bxw waves side by side),
@@ -29,9 +31,11 @@ struct StencilArgs {
     const void *q;       // point operand (f, or u_t); unused by SOP_LAP
     void *out;           // output field
     double *partials;    // [nblk][2] per-workgroup sums, or null
+    void *lam;           // SOP_ADJL: running sum of the adjoint inputs
     int64_t nx, ny, nz;
     double c0, c1, c2;
     int tiles_x, tiles_y, zc, nblk;
+    int lam_first;
 };
 
 // Tile shapes compiled into the library, in preference order.
@@ -48,7 +52,7 @@ hipError_t launch_stencil(int dtype, int op, int bc, bool reduce, const Tile &t,
 
 // Element-wise statements of the unfused program, and a plain copy (o = x)
 // used for checkpoint slots and copy-backs.
-enum EwOp : int { EW_POW3 = 0, EW_SCALE = 1, EW_SUB = 2, EW_ADD = 3, EW_COPY = 4 };
+enum EwOp : int { EW_POW3 = 0, EW_SCALE = 1, EW_SUB = 2, EW_ADD = 3, EW_COPY = 4, EW_ZERO = 5 };
 hipError_t launch_ew(int dtype, int op, const void *x, const void *y, void *o,
                      double a, int64_t n, bool vec_ok, hipStream_t stream);
 
@@ -57,6 +61,13 @@ int ew_norm_blocks(int64_t n);
 hipError_t launch_ew_norms(int dtype, const void *o, const void *u,
                            double *partials, int64_t n, bool vec_ok,
                            hipStream_t stream);
+// Per-workgroup sums {sum a*b, 0} in double (ew_norm_blocks(n) workgroups).
+hipError_t launch_ew_dot(int dtype, const void *a, const void *b,
+                         double *partials, int64_t n, bool vec_ok,
+                         hipStream_t stream);
+// dst[0] = s * src[0].
+hipError_t launch_scalar_scale(const double *src, double s, double *dst,
+                               hipStream_t stream);
 
 // Two fused steps per pass (temporal blocking): full-row slabs of ty rows,
 // zc planes per run, one 1024-lane workgroup per slab-run.
@@ -64,6 +75,8 @@ hipError_t launch_ew_norms(int dtype, const void *o, const void *u,
 //            part1/part2 = norms of steps t+1 / t+2 (or null)
 //   SOP_ADJ: u = lambda_{t+1}, f = u_t, g2 = u_{t-1}, out = lambda_{t-1};
 //            part1/part2 = parameter sums of steps t / t-1
+//   SOP_ADJL: SOP_ADJ, and lam = (lam + lambda_{t+1}) + lambda_t on the owned
+//            points (lam_first: lam is not read, taken as 0)
 struct TbArgs {
     const void *u;
     const void *f;
@@ -72,9 +85,11 @@ struct TbArgs {
     void *mid;
     double *part1;      // [nblk][2]
     double *part2;      // [nblk][2]
+    void *lam;
     int64_t nx, ny, nz;
     double c0, c1, c2;
     int nslab, zc;
+    int lam_first;
 };
 struct TbTile {
     int vec, ty, nt, km, zc, nslab, nruns, nblk;

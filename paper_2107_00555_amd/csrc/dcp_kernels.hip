@@ -244,6 +244,16 @@ __global__ void __launch_bounds__(64 * BXW * BY) stencil_kernel(StencilArgs a) {
                         }
                     }
                     store_vec<T, VEC>(O + z * sz + (yf + r) * sy + x0, res);
+                    if constexpr (OP == SOP_ADJL) {
+                        // running sum of the adjoint inputs: lam += lambda_{t+1}
+                        T *lp = static_cast<T *>(a.lam) + z * sz + (yf + r) * sy + x0;
+                        T lv[VEC];
+                        if (a.lam_first) zero_vec<T, VEC>(lv);
+                        else load_vec<T, VEC>(lv, lp);
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) lv[e] = lv[e] + uc[r][e];
+                        store_vec<T, VEC>(lp, lv);
+                    }
                 }
             }
         }
@@ -316,6 +326,8 @@ hipError_t launch_shape(int op, int bc, bool reduce, int nblk, const StencilArgs
             else DCP_L(0, SOP_FWD, false);
         } else if (op == SOP_ADJ) {
             DCP_L(0, SOP_ADJ, true);
+        } else if (op == SOP_ADJL) {
+            DCP_L(0, SOP_ADJL, true);
         } else {
             DCP_L(0, SOP_LAP, false);
         }
@@ -325,6 +337,8 @@ hipError_t launch_shape(int op, int bc, bool reduce, int nblk, const StencilArgs
             else DCP_L(1, SOP_FWD, false);
         } else if (op == SOP_ADJ) {
             DCP_L(1, SOP_ADJ, true);
+        } else if (op == SOP_ADJL) {
+            DCP_L(1, SOP_ADJL, true);
         } else {
             DCP_L(1, SOP_LAP, false);
         }
@@ -361,6 +375,7 @@ __device__ __forceinline__ void ew_apply(T (&o)[VEC], const T (&x)[VEC], const T
         else if constexpr (OPC == EW_SCALE) o[i] = a * x[i];
         else if constexpr (OPC == EW_SUB) o[i] = x[i] - y[i];
         else if constexpr (OPC == EW_ADD) o[i] = x[i] + y[i];
+        else if constexpr (OPC == EW_ZERO) o[i] = T(0);
         else o[i] = x[i];
     }
 }
@@ -382,7 +397,8 @@ __global__ void __launch_bounds__(256)
         for (int u = 0; u < U; ++u) {
             const int64_t i = j + u * 256;
             if (i < end) {
-                load_vec<T, VEC>(xv[u], x + i * VEC);
+                if constexpr (OPC != EW_ZERO) load_vec<T, VEC>(xv[u], x + i * VEC);
+                else zero_vec<T, VEC>(xv[u]);
                 if constexpr (BIN) load_vec<T, VEC>(yv[u], y + i * VEC);
                 else zero_vec<T, VEC>(yv[u]);
             }
@@ -399,7 +415,7 @@ __global__ void __launch_bounds__(256)
     if (blockIdx.x == 0) {
         const int64_t t = nv * VEC + threadIdx.x;
         if (t < n) {
-            T xs[1] = {x[t]}, ys[1] = {BIN ? y[t] : T(0)}, os[1];
+            T xs[1] = {OPC == EW_ZERO ? T(0) : x[t]}, ys[1] = {BIN ? y[t] : T(0)}, os[1];
             ew_apply<T, 1, OPC>(os, xs, ys, a);
             o[t] = os[0];
         }
@@ -424,7 +440,8 @@ __device__ __forceinline__ void block_sum2_256(double &a0, double &a1, double (*
     }
 }
 
-template <typename T, int VEC>
+// DOT = false: {sum o^2, sum (o - u)^2};  DOT = true: {sum o*u, 0}.
+template <typename T, int VEC, bool DOT>
 __global__ void __launch_bounds__(256)
     ew_norms_kernel(const T *__restrict__ o, const T *__restrict__ u, double *__restrict__ partials,
                     int64_t n) {
@@ -432,25 +449,25 @@ __global__ void __launch_bounds__(256)
     const int64_t nv = n / VEC;
     const int64_t stride = (int64_t)gridDim.x * 256;
     double a0 = 0.0, a1 = 0.0;
+    auto term = [&](T ov, T uv) {
+        const double d = (double)ov;
+        if constexpr (DOT) {
+            a0 += d * (double)uv;
+        } else {
+            a0 += d * d;
+            const double dd = d - (double)uv;
+            a1 += dd * dd;
+        }
+    };
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nv; i += stride) {
         T ov[VEC], uv[VEC];
         load_vec<T, VEC>(ov, o + i * VEC);
         load_vec<T, VEC>(uv, u + i * VEC);
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) {
-            const double d = (double)ov[e];
-            a0 += d * d;
-            const double dd = d - (double)uv[e];
-            a1 += dd * dd;
-        }
+        for (int e = 0; e < VEC; ++e) term(ov[e], uv[e]);
     }
     const int64_t t = nv * VEC + (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t < n) {
-        const double d = (double)o[t];
-        a0 += d * d;
-        const double dd = d - (double)u[t];
-        a1 += dd * dd;
-    }
+    if (t < n) term(o[t], u[t]);
     block_sum2_256(a0, a1, red);
     if (threadIdx.x == 0) {
         partials[2 * blockIdx.x] = a0;
@@ -502,6 +519,10 @@ __global__ void grad_finalize_kernel(const double *__restrict__ sums, int nsteps
     grad[1] = s1 * (sb + cb);
 }
 
+__global__ void scalar_scale_kernel(const double *src, double s, double *dst) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) dst[0] = s * src[0];
+}
+
 __global__ void zero_kernel(double *dst, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dst[i] = 0.0;
@@ -532,6 +553,7 @@ hipError_t launch_ew_t(int op, const void *x, const void *y, void *o, double a, 
             case EW_SCALE: DCP_EW(W, EW_SCALE); break;
             case EW_SUB: DCP_EW(W, EW_SUB); break;
             case EW_ADD: DCP_EW(W, EW_ADD); break;
+            case EW_ZERO: DCP_EW(W, EW_ZERO); break;
             default: DCP_EW(W, EW_COPY); break;
         }
     } else {
@@ -540,6 +562,7 @@ hipError_t launch_ew_t(int op, const void *x, const void *y, void *o, double a, 
             case EW_SCALE: DCP_EW(1, EW_SCALE); break;
             case EW_SUB: DCP_EW(1, EW_SUB); break;
             case EW_ADD: DCP_EW(1, EW_ADD); break;
+            case EW_ZERO: DCP_EW(1, EW_ZERO); break;
             default: DCP_EW(1, EW_COPY); break;
         }
     }
@@ -580,18 +603,38 @@ int ew_norm_blocks(int64_t n) {
     return (int)b;
 }
 
-hipError_t launch_ew_norms(int dtype, const void *o, const void *u, double *partials, int64_t n,
-                           bool vec_ok, hipStream_t st) {
+template <bool DOT>
+hipError_t launch_ew_red(int dtype, const void *o, const void *u, double *partials, int64_t n, bool vec_ok,
+                         hipStream_t st) {
     const int nb = ew_norm_blocks(n);
     if (dtype == 0) {
         const double *O = static_cast<const double *>(o), *U = static_cast<const double *>(u);
-        if (vec_ok) hipLaunchKernelGGL((ew_norms_kernel<double, 2>), dim3(nb), dim3(256), 0, st, O, U, partials, n);
-        else hipLaunchKernelGGL((ew_norms_kernel<double, 1>), dim3(nb), dim3(256), 0, st, O, U, partials, n);
+        if (vec_ok)
+            hipLaunchKernelGGL((ew_norms_kernel<double, 2, DOT>), dim3(nb), dim3(256), 0, st, O, U, partials, n);
+        else
+            hipLaunchKernelGGL((ew_norms_kernel<double, 1, DOT>), dim3(nb), dim3(256), 0, st, O, U, partials, n);
     } else {
         const float *O = static_cast<const float *>(o), *U = static_cast<const float *>(u);
-        if (vec_ok) hipLaunchKernelGGL((ew_norms_kernel<float, 4>), dim3(nb), dim3(256), 0, st, O, U, partials, n);
-        else hipLaunchKernelGGL((ew_norms_kernel<float, 1>), dim3(nb), dim3(256), 0, st, O, U, partials, n);
+        if (vec_ok)
+            hipLaunchKernelGGL((ew_norms_kernel<float, 4, DOT>), dim3(nb), dim3(256), 0, st, O, U, partials, n);
+        else
+            hipLaunchKernelGGL((ew_norms_kernel<float, 1, DOT>), dim3(nb), dim3(256), 0, st, O, U, partials, n);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_ew_norms(int dtype, const void *o, const void *u, double *partials, int64_t n,
+                           bool vec_ok, hipStream_t st) {
+    return launch_ew_red<false>(dtype, o, u, partials, n, vec_ok, st);
+}
+
+hipError_t launch_ew_dot(int dtype, const void *a, const void *b, double *partials, int64_t n, bool vec_ok,
+                         hipStream_t st) {
+    return launch_ew_red<true>(dtype, a, b, partials, n, vec_ok, st);
+}
+
+hipError_t launch_scalar_scale(const double *src, double s, double *dst, hipStream_t st) {
+    hipLaunchKernelGGL(scalar_scale_kernel, dim3(1), dim3(64), 0, st, src, s, dst);
     return hipGetLastError();
 }
 

@@ -131,7 +131,8 @@ template <typename T, int VEC, int TY, int NT, int KM, int BC, int OP, bool RED,
 __global__ void __launch_bounds__(NT) tb2_kernel(TbArgs a) {
     constexpr int kTbThreads = NT;
     constexpr int kTbKmax = KM;
-    constexpr bool ADJ = (OP == SOP_ADJ);
+    constexpr bool ADJ = (OP == SOP_ADJ || OP == SOP_ADJL);
+    constexpr bool LAM = (OP == SOP_ADJL);
     extern __shared__ __align__(16) unsigned char tb_smem[];
     constexpr int R0 = TY + 4;  // level-0 rows: global rows y0-2 .. y0+TY+1
     constexpr int R1 = TY + 2;  // level-1 rows: global rows y0-1 .. y0+TY
@@ -336,6 +337,17 @@ __global__ void __launch_bounds__(NT) tb2_kernel(TbArgs a) {
                     }
                 }
                 tb_store<T, VEC>(O + (int64_t)(q - 1) * sz + gofs[k], res);
+                if constexpr (LAM) {
+                    // running sum of the adjoint inputs, in step order:
+                    // lam = (lam + lambda_{t+1}) + lambda_t (level 0 at q-1 is in am)
+                    T *lp = static_cast<T *>(a.lam) + (int64_t)(q - 1) * sz + gofs[k];
+                    T lv[VEC];
+                    if (a.lam_first) tb_zero<T, VEC>(lv);
+                    else tb_load<T, VEC>(lv, lp);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) lv[e] = (lv[e] + am[k][e]) + c[e];
+                    tb_store<T, VEC>(lp, lv);
+                }
                 if constexpr (RED && !ADJ) {
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) {
@@ -414,6 +426,9 @@ hipError_t tb_launch_t(int op, int bc, bool reduce, bool mid, const TbTile &t, c
     if (op == SOP_ADJ) {
         if (bc == 0) DCP_TB(0, SOP_ADJ, true, false);
         else DCP_TB(1, SOP_ADJ, true, false);
+    } else if (op == SOP_ADJL) {
+        if (bc == 0) DCP_TB(0, SOP_ADJL, true, false);
+        else DCP_TB(1, SOP_ADJL, true, false);
     } else if (mid) {
         if (bc == 0) DCP_TB(0, SOP_FWD, false, true);
         else DCP_TB(1, SOP_FWD, false, true);

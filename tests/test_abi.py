@@ -143,10 +143,10 @@ def test_run_argument_errors(L):
 
 
 def adj_call(L, dtype=0, ckpt=0x50000000, k=2, f=F, lam=U, n=(8, 8, 8), c=None, bc=0, T=4, tb=1,
-             g=O, gab=0x60000000, ws=WS, wsb=1 << 26):
+             g=O, gab=0x60000000, gf=None, gg=None, ws=WS, wsb=1 << 26):
     c = coeffs(L) if c is None else c
     return L.lib().dcp_adjoint_run(dtype, ckpt, k, f, lam, n[0], n[1], n[2], ctypes.byref(c), bc,
-                                   T, tb, g, gab, ws, wsb, None)
+                                   T, tb, g, gab, gf, gg, ws, wsb, None)
 
 
 def test_adjoint_argument_errors(L):
@@ -161,6 +161,19 @@ def test_adjoint_argument_errors(L):
     assert adj_call(L, c=coeffs(L, beta=float("-inf"))) == -5
     assert adj_call(L, tb=0) == -5
     assert adj_call(L, tb=3) == -5
+    assert adj_call(L, gf=F) == -7              # grad_f aliases f
+    assert adj_call(L, gf=O + 8) == -7          # grad_f overlaps grad_u0
+    assert adj_call(L, gf=WS + 64) == -7        # grad_f inside the workspace
+    assert adj_call(L, gf=0x68000000, gg=0x60000008) == -7   # grad_gamma overlaps grad_ab
+    assert adj_call(L, gf=0x68000000, gg=0x68000000) == -7   # grad_gamma inside grad_f
+
+
+def test_adjoint_workspace_for_gamma_without_f(L):
+    base = L.workspace_bytes(L.OP_ADJOINT, L.F64, 64, 64, 64, T=10, ckpt_every=5)
+    extra = L.workspace_bytes(L.OP_ADJOINT, L.F64, 64, 64, 64, T=10, ckpt_every=5, norms=True)
+    assert extra - base == 64 * 64 * 64 * 8      # one more field for the running sum
+    # a call asking for grad_gamma without grad_f needs the larger workspace
+    assert adj_call(L, n=(64, 64, 64), T=10, k=5, gg=0x60000010, wsb=base) == -6
 
 
 # ------------------------------------------------------------------ Jacobi
