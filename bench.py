@@ -411,6 +411,41 @@ def main():
         ms_ga /= kk
         forms["gradient_f64_T100_k10_all_inputs"] = {"ms": round(ms_ga, 3),
                                                      "ms_over_forward": round(ms_ga / ms_step, 3)}
+        del ck, wsf, wsa
+
+        # memory-bounded gradient over T=1000 steps: binomial checkpointing
+        # with 8 snapshots against a checkpoint every 32 steps
+        Tr, slots, kr = 1000, 8, 32
+        GiB = float(1 << 30)
+        log(f"timing gradient f64 T={Tr}: binomial checkpointing with {slots} snapshots")
+
+        def rev_grad():
+            ug.copy_(u0)
+            wsr = api.revolve_forward(ug, f64, coeffs, Tr, bc, slots, tblock=args.tblock)
+            api.revolve_adjoint(wsr, f64, ug, coeffs, Tr, bc, slots, tblock=args.tblock)
+
+        ms_r, _, _ = timed(rev_grad, 2, 1, stream)
+        ms_r /= 2
+        _, fwd_steps = _lib.revolve_schedule(Tr, slots)
+        mem_r = _lib.revolve_workspace_bytes(_lib.F64, nx, ny, nz, Tr, slots)
+        log(f"timing gradient f64 T={Tr}: checkpoint every {kr} steps")
+        ck = torch.empty(((Tr + kr - 1) // kr, nz, ny, nx), dtype=torch.float64, device=dev)
+        wsf = api.workspace(_lib.workspace_bytes(_lib.OP_RUN, _lib.F64, nx, ny, nz, T=Tr, tblock=2), dev)
+        wsa = api.workspace(_lib.workspace_bytes(_lib.OP_ADJOINT, _lib.F64, nx, ny, nz, T=Tr, ckpt_every=kr), dev)
+
+        def uni_grad():
+            ug.copy_(u0)
+            api.run(ug, f64, coeffs, Tr, bc, tblock=args.tblock, norms=False, ckpt_every=kr, ws=wsf, ckpt=ck)
+            api.adjoint_run(ck, kr, f64, ug, coeffs, Tr, bc, ws=wsa, grad_u0=g)
+
+        ms_u1, _, _ = timed(uni_grad, 2, 1, stream)
+        ms_u1 /= 2
+        mem_u = ck.numel() * 8 + wsa.numel() + (wsf.numel() if wsf is not None else 0)
+        forms[f"gradient_f64_T{Tr}_revolve{slots}"] = {
+            "ms": round(ms_r, 1), "forward_steps": int(fwd_steps) + 1, "adjoint_steps": Tr,
+            "device_memory_gib": round(mem_r / GiB, 2),
+            "vs_checkpoint_every_32": {"ms": round(ms_u1, 1), "forward_steps": 2 * Tr - (Tr + kr - 1) // kr,
+                                       "device_memory_gib": round(mem_u / GiB, 2)}}
         del ck, wsf, wsa, g, ug, u32, f32
 
     # ------------------------------------------------ the Jacobi listings

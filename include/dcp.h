@@ -270,6 +270,63 @@ int dcp_jacobi_2d(int32_t tsteps, double *A, double *B, int64_t n0,
                   int64_t n1, int32_t tblock, void *ws, size_t ws_bytes,
                   void *stream);
 
+/*
+ * Gradient through T fused steps with a fixed number of stored states
+ * (binomial checkpointing): the memory-bounded alternative to checkpoints
+ * every k steps, for T much larger than memory allows.  The reverse sweep
+ * follows the schedule of dcp_revolve_schedule: with nslots snapshot slots
+ * it recomputes the least number of forward steps (r*T - C(c+r, c+1) with
+ * c = nslots + 1 and r the least integer with C(c+r, c) >= T).
+ *
+ * dcp_revolve_workspace_bytes: the workspace both calls share (the caller
+ *   keeps it, untouched, from the forward call to the adjoint call): the
+ *   saved u_0, nslots + 1 states, one scratch and two adjoint fields, plus
+ *   the reductions; lsum_field nonzero adds the field for grad_gamma without
+ *   grad_f.  Writes *bytes (host pointer).
+ * dcp_revolve_forward: T steps in place on u (u_0 in, u_T out), as dcp_run
+ *   computes them (bitwise the same u_T), saving u_0 and the snapshots the
+ *   reverse sweep starts from in ws.  tblock as in dcp_run (1 or 2).
+ * dcp_revolve_adjoint: the same outputs as dcp_adjoint_run (grad_u0,
+ *   grad_ab, optional grad_f and grad_gamma), from lam_T = dL/du_T and the
+ *   workspace of the forward call (same T, nslots, coefficients, boundary
+ *   and dtype).  The reverse sweep reuses the snapshot slots, so one
+ *   forward call serves one adjoint call (run the forward again for
+ *   another).  Adjoint steps run one per pass, so grad_u0, grad_ab,
+ *   grad_f and grad_gamma equal dcp_adjoint_run's with tblock = 1 bit for
+ *   bit; tblock applies to the recomputed forward steps.
+ * Arguments, ownership and errors as for dcp_run / dcp_adjoint_run.
+ */
+int dcp_revolve_workspace_bytes(int dtype, int64_t nx, int64_t ny,
+                                int64_t nz, int32_t T, int32_t nslots,
+                                int lsum_field, size_t *bytes);
+
+int dcp_revolve_forward(int dtype, void *u, const void *f, int64_t nx,
+                        int64_t ny, int64_t nz, const dcp_coeffs *coeffs,
+                        int bc, int32_t T, int32_t nslots, int32_t tblock,
+                        void *ws, size_t ws_bytes, void *stream);
+
+int dcp_revolve_adjoint(int dtype, const void *f, const void *lam_T,
+                        int64_t nx, int64_t ny, int64_t nz,
+                        const dcp_coeffs *coeffs, int bc, int32_t T,
+                        int32_t nslots, int32_t tblock, void *grad_u0,
+                        double *grad_ab, void *grad_f, double *grad_gamma,
+                        void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Binomial checkpointing schedule of the reverse sweep over T steps with
+ * `nslots` snapshot slots (besides the saved u_0 and one work state); see
+ * dcp_revolve_forward / dcp_revolve_adjoint.  Writes *nops and, if not NULL,
+ * *forward_steps (steps recomputed by the schedule, including the initial
+ * sweep to u_{T-1}); if ops is not NULL, also the ops as 5 int64 each:
+ *   {0, src, dst, t0, t1}  advance the state in buffer src (time t0) to time
+ *                          t1 into buffer dst
+ *   {1, src, -1, t, t}     adjoint step t with u_t in buffer src
+ * Buffers: -1 = the saved u_0, 0 .. nslots-1 = slots, nslots = work state.
+ * DCP_E_WORKSPACE if cap (in ops) is too small.  Host only.
+ */
+int dcp_revolve_schedule(int64_t T, int32_t nslots, int64_t *ops, int64_t cap,
+                         int64_t *nops, int64_t *forward_steps);
+
 /* Static, NUL-terminated description of a dcp_status value. */
 const char *dcp_status_string(int status);
 

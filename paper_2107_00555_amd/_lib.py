@@ -78,6 +78,16 @@ def lib() -> ctypes.CDLL:
     L.dcp_max_tblock.restype = i32
     L.dcp_jacobi_workspace_bytes.argtypes = [c_int, i64, i64, i32, i32, ctypes.POINTER(sz)]
     L.dcp_jacobi_workspace_bytes.restype = c_int
+    L.dcp_revolve_workspace_bytes.argtypes = [c_int, i64, i64, i64, i32, i32, c_int, ctypes.POINTER(sz)]
+    L.dcp_revolve_workspace_bytes.restype = c_int
+    L.dcp_revolve_forward.argtypes = [c_int, vp, vp, i64, i64, i64, cp, c_int, i32, i32, i32, vp, sz, vp]
+    L.dcp_revolve_forward.restype = c_int
+    L.dcp_revolve_adjoint.argtypes = [c_int, vp, vp, i64, i64, i64, cp, c_int, i32, i32, i32, vp, dp, vp, dp,
+                                      vp, sz, vp]
+    L.dcp_revolve_adjoint.restype = c_int
+    i64p = ctypes.POINTER(i64)
+    L.dcp_revolve_schedule.argtypes = [i64, i32, i64p, i64, i64p, i64p]
+    L.dcp_revolve_schedule.restype = c_int
     L.dcp_jacobi_plan.argtypes = [c_int, i64, i64, i32, i32, ctypes.POINTER(i64), ctypes.POINTER(i32)]
     L.dcp_jacobi_plan.restype = c_int
     L.dcp_jacobi_1d.argtypes = [i32, vp, vp, i64, i32, vp, sz, vp]
@@ -116,3 +126,25 @@ def jacobi_plan(dims: int, n0: int, n1: int, tsteps: int, tblock: int = 0) -> tu
     check("dcp_jacobi_plan",
           lib().dcp_jacobi_plan(dims, n0, n1, tsteps, tblock, ctypes.byref(passes), ctypes.byref(halo)))
     return passes.value, halo.value
+
+
+def revolve_schedule(T: int, nslots: int):
+    """(ops as a list of (kind, src, dst, t0, t1), forward steps) of the
+    binomial checkpointing schedule (see dcp.h)."""
+    n, fwd = ctypes.c_int64(0), ctypes.c_int64(0)
+    check("dcp_revolve_schedule", lib().dcp_revolve_schedule(T, nslots, None, 0, ctypes.byref(n),
+                                                              ctypes.byref(fwd)))
+    buf = (ctypes.c_int64 * (5 * max(n.value, 1)))()
+    check("dcp_revolve_schedule", lib().dcp_revolve_schedule(T, nslots, buf, n.value, ctypes.byref(n),
+                                                              ctypes.byref(fwd)))
+    ops = [tuple(buf[5 * i:5 * i + 5]) for i in range(n.value)]
+    return ops, fwd.value
+
+
+def revolve_workspace_bytes(dtype: int, nx: int, ny: int, nz: int, T: int, nslots: int,
+                            lsum_field: bool = False) -> int:
+    out = ctypes.c_size_t(0)
+    check("dcp_revolve_workspace_bytes",
+          lib().dcp_revolve_workspace_bytes(dtype, nx, ny, nz, T, nslots, int(bool(lsum_field)),
+                                            ctypes.byref(out)))
+    return out.value

@@ -17,7 +17,7 @@ from ._lib import (DIRICHLET0, F32, F64, FUSED, OP_ADJOINT, OP_RUN, OP_STEP_FUSE
 
 __all__ = ["Coeffs", "DcpError", "DIRICHLET0", "PERIODIC", "FUSED", "UNFUSED",
            "step", "run", "adjoint_run", "workspace", "num_slots", "bc_code", "impl_code",
-           "jacobi_1d", "jacobi_2d"]
+           "jacobi_1d", "jacobi_2d", "revolve_forward", "revolve_adjoint"]
 
 
 def bc_code(bc) -> int:
@@ -155,6 +155,52 @@ def adjoint_run(ckpt: torch.Tensor | None, ckpt_every: int, f: torch.Tensor, lam
     _lib.check("dcp_adjoint_run", _lib.lib().dcp_adjoint_run(
         dt, _ptr(ckpt), int(ckpt_every), _ptr(f), _ptr(lam_T), nx, ny, nz, ctypes.byref(c),
         bc_code(bc), int(T), int(tblock), _ptr(grad_u0), _ptr(gab), _ptr(gf), _ptr(gg), _ptr(ws), wsb,
+        _stream(lam_T.device)))
+    if not (want_f or want_gamma):
+        return grad_u0, gab
+    out = {"u0": grad_u0, "ab": gab}
+    if want_f:
+        out["f"] = gf
+    if want_gamma:
+        out["gamma"] = gg[0]
+    return out
+
+def revolve_forward(u: torch.Tensor, f: torch.Tensor, coeffs, T: int, bc, nslots: int, tblock: int = 2,
+                    reserve_sum: bool = False) -> torch.Tensor:
+    """T steps in place on u with binomial checkpointing snapshots; returns
+    the workspace tensor the matching revolve_adjoint call needs (keep it
+    untouched).  reserve_sum: room for dL/dgamma without dL/df."""
+    u = _field("u", u)
+    f = _field("f", f, u)
+    dt = _dtype_code(u)
+    nz, ny, nx = u.shape
+    c = Coeffs.make(coeffs)
+    wsb = _lib.revolve_workspace_bytes(dt, nx, ny, nz, T, nslots, reserve_sum)
+    ws = workspace(wsb, u.device)
+    _lib.check("dcp_revolve_forward", _lib.lib().dcp_revolve_forward(
+        dt, _ptr(u), _ptr(f), nx, ny, nz, ctypes.byref(c), bc_code(bc), int(T), int(nslots), int(tblock),
+        _ptr(ws), wsb, _stream(u.device)))
+    return ws if ws is not None else torch.empty(0, dtype=torch.uint8, device=u.device)
+
+
+def revolve_adjoint(ws: torch.Tensor, f: torch.Tensor, lam_T: torch.Tensor, coeffs, T: int, bc, nslots: int,
+                    tblock: int = 2, want_f: bool = False, want_gamma: bool = False):
+    """The gradient from revolve_forward's workspace; returns like adjoint_run."""
+    lam_T = _field("lam_T", lam_T)
+    f = _field("f", f, lam_T)
+    dt = _dtype_code(lam_T)
+    nz, ny, nx = lam_T.shape
+    c = Coeffs.make(coeffs)
+    wsb = _lib.revolve_workspace_bytes(dt, nx, ny, nz, T, nslots, want_gamma and not want_f)
+    if ws.numel() < wsb:
+        raise ValueError("workspace smaller than this call needs (reserve_sum in revolve_forward?)")
+    grad_u0 = torch.empty_like(lam_T)
+    gab = torch.empty(2, dtype=torch.float64, device=lam_T.device)
+    gf = torch.empty_like(lam_T) if want_f else None
+    gg = torch.empty(1, dtype=torch.float64, device=lam_T.device) if want_gamma else None
+    _lib.check("dcp_revolve_adjoint", _lib.lib().dcp_revolve_adjoint(
+        dt, _ptr(f), _ptr(lam_T), nx, ny, nz, ctypes.byref(c), bc_code(bc), int(T), int(nslots), int(tblock),
+        _ptr(grad_u0), _ptr(gab), _ptr(gf), _ptr(gg), _ptr(ws) if ws.numel() else None, ws.numel(),
         _stream(lam_T.device)))
     if not (want_f or want_gamma):
         return grad_u0, gab

@@ -380,6 +380,91 @@ int step_common(int impl, int dtype, const void *u, const void *f, void *u_out, 
 
 int32_t num_slots(int32_t T, int32_t k) { return T <= 0 ? 0 : (T + k - 1) / k; }
 
+// ------------------------------------------------ binomial checkpointing
+// Workspace of the two revolve calls (kept by the caller between them):
+// the saved u_0, nslots snapshot slots, the work state, an advance scratch
+// field, two adjoint fields, optionally the running sum of the adjoint
+// inputs, and the reduction scratch of the adjoint.
+struct RevWs {
+    size_t origin = 0, slots = 0, work = 0, scratch = 0, lam = 0, lsum = 0;
+    size_t partials = 0, sums = 0, dot = 0;
+    int nblk = 0;
+    size_t total = 0;
+};
+
+int layout_rev(int dtype, const Geo &g, int32_t T, int32_t nslots, bool lsum_field, RevWs *w) {
+    size_t off = 0;
+    if (T == 0 || g.n == 0) {
+        w->total = 0;
+        return DCP_OK;
+    }
+    const size_t fb = align_up(g.bytes());
+    const int nb = max_blocks(dtype, g);
+    if (nb < 0) return DCP_E_SHAPE;
+    w->nblk = nb;
+    w->origin = off;
+    off += fb;
+    w->slots = off;
+    off += (size_t)nslots * fb;
+    w->work = off;
+    off += fb;
+    w->scratch = off;
+    off += fb;
+    w->lam = off;
+    off += 2 * fb;
+    if (lsum_field) {
+        w->lsum = off;
+        off += fb;
+    }
+    w->partials = off;
+    off += align_up((size_t)T * nb * 2 * sizeof(double));
+    w->sums = off;
+    off += align_up((size_t)T * 2 * sizeof(double));
+    w->dot = off;
+    off += align_up(((size_t)ew_norm_blocks(g.n) * 2 + 2) * sizeof(double));
+    w->total = off;
+    return DCP_OK;
+}
+
+struct RevBufs {
+    void *ws;
+    const RevWs *w;
+    int32_t nslots;
+    size_t fb;
+    void *buf(int32_t id) const {
+        if (id == kRvOrigin) return at(ws, w->origin);
+        if (id < nslots) return at(ws, w->slots + (size_t)id * fb);
+        return at(ws, w->work);
+    }
+};
+
+// n fused steps from `from` into `to` (n >= 1; both distinct from the
+// scratch field), two per pass where the grid allows it, alternating between
+// `to` and the scratch so the last step lands in `to`.
+int rev_advance(int dtype, int bc, const Geo &g, const dcp_coeffs &c, const Tile &t, bool use_tb,
+                const TbTile &tb, const void *f, const void *from, void *to, void *scratch, int64_t n,
+                hipStream_t st) {
+    std::vector<int> lens;
+    for (int64_t left = n; left > 0;) {
+        const int k = (use_tb && left >= 2) ? 2 : 1;
+        lens.push_back(k);
+        left -= k;
+    }
+    const void *cur = from;
+    const size_t L = lens.size();
+    for (size_t i = 0; i < L; ++i) {
+        void *out = ((L - 1 - i) % 2 == 0) ? to : scratch;
+        if (lens[i] == 2) {
+            if (tb_fwd_pass(dtype, bc, g, c, tb, cur, f, out, nullptr, nullptr, nullptr, st) != hipSuccess)
+                return DCP_E_HIP;
+        } else if (fused_step(dtype, bc, g, c, t, cur, f, out, nullptr, st) != hipSuccess) {
+            return DCP_E_HIP;
+        }
+        cur = out;
+    }
+    return DCP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -700,6 +785,172 @@ int dcp_adjoint_run(int dtype, const void *ckpt, int32_t ckpt_every, const void 
     if (lsum) {
         // dL/dgamma = dt * <sum, f> (fixed-order double reduction), then
         // dL/df = gamma * dt * sum in place
+        if (grad_gamma) {
+            double *dp = reinterpret_cast<double *>(at(ws, w.dot));
+            const int nb = ew_norm_blocks(g.n);
+            double *pair = dp + 2 * (size_t)nb;
+            DCP_TRY(launch_ew_dot(dtype, lsum, f, dp, g.n, vec_ok_for(dtype, g, {lsum, f}), st));
+            DCP_TRY(launch_finalize(dp, nb, nb, 1, pair, nullptr, 0, st));
+            DCP_TRY(launch_scalar_scale(pair, c.dt, grad_gamma, st));
+        }
+        if (grad_f)
+            DCP_TRY(launch_ew(dtype, EW_SCALE, grad_f, nullptr, grad_f, c.gamma * c.dt, g.n,
+                              vec_ok_for(dtype, g, {grad_f}), st));
+    }
+    return DCP_OK;
+}
+
+int dcp_revolve_workspace_bytes(int dtype, int64_t nx, int64_t ny, int64_t nz, int32_t T, int32_t nslots,
+                                int lsum_field, size_t *bytes) {
+    if (!bytes) return DCP_E_NULL;
+    Geo g;
+    int rc = check_geo(dtype, nx, ny, nz, &g);
+    if (rc) return rc;
+    if (T < 0 || nslots < 0) return DCP_E_ARG;
+    RevWs w;
+    if ((rc = layout_rev(dtype, g, T, nslots, lsum_field != 0, &w))) return rc;
+    *bytes = w.total;
+    return DCP_OK;
+}
+
+int dcp_revolve_forward(int dtype, void *u, const void *f, int64_t nx, int64_t ny, int64_t nz,
+                        const dcp_coeffs *coeffs, int bc, int32_t T, int32_t nslots, int32_t tblock, void *ws,
+                        size_t ws_bytes, void *stream) {
+    Geo g;
+    int rc = check_geo(dtype, nx, ny, nz, &g);
+    if (rc) return rc;
+    if (bc != DCP_DIRICHLET0 && bc != DCP_PERIODIC) return DCP_E_BC;
+    if ((rc = check_coeffs(coeffs))) return rc;
+    if (T < 0 || nslots < 0 || tblock < 1 || tblock > dcp_max_tblock(dtype)) return DCP_E_ARG;
+    if (g.n > 0 && (!u || !f)) return DCP_E_NULL;
+    RevWs w;
+    if ((rc = layout_rev(dtype, g, T, nslots, false, &w))) return rc;
+    // the running-sum field, if any, sits after the fields used here
+    if ((rc = check_ws(ws, ws_bytes, w.total))) return rc;
+    const size_t fb = g.bytes();
+    if (overlaps(u, fb, f, fb) || overlaps(ws, ws_bytes, u, fb) || overlaps(ws, ws_bytes, f, fb)) return DCP_E_ALIAS;
+    if (T == 0 || g.n == 0) return DCP_OK;
+    std::vector<RvOp> ops;
+    if (!revolve_schedule(T, nslots, &ops, nullptr)) return DCP_E_ARG;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const RevBufs B{ws, &w, nslots, align_up(fb)};
+    void *scratch = at(ws, w.scratch);
+    bool vok = vec_ok_for(dtype, g, {u, f, B.buf(kRvOrigin), B.buf(nslots), scratch});
+    for (int32_t i = 0; i < nslots; ++i) vok = vok && aligned16(B.buf(i));
+    const Tile t = pick_tile(dtype, g, vok);
+    TbTile tb{};
+    const bool use_tb = plan_tb(dtype, g, tblock, vok, &tb);
+    const dcp_coeffs &c = *coeffs;
+    DCP_TRY(launch_ew(dtype, EW_COPY, u, nullptr, B.buf(kRvOrigin), 0.0, g.n, vok, st));
+    // the schedule's opening chain of advances, u_0 -> ... -> u_{T-1}, stores
+    // the snapshots the reverse sweep starts from
+    int32_t last = kRvOrigin;
+    for (const RvOp &op : ops) {
+        if (op.kind != kRvAdvance) break;
+        if ((rc = rev_advance(dtype, bc, g, c, t, use_tb, tb, f, B.buf(op.src), B.buf(op.dst), scratch,
+                              op.t1 - op.t0, st)))
+            return rc;
+        last = op.dst;
+    }
+    DCP_TRY(fused_step(dtype, bc, g, c, t, B.buf(last), f, u, nullptr, st));  // u_T
+    return DCP_OK;
+}
+
+int dcp_revolve_adjoint(int dtype, const void *f, const void *lam_T, int64_t nx, int64_t ny, int64_t nz,
+                        const dcp_coeffs *coeffs, int bc, int32_t T, int32_t nslots, int32_t tblock,
+                        void *grad_u0, double *grad_ab, void *grad_f, double *grad_gamma, void *ws,
+                        size_t ws_bytes, void *stream) {
+    Geo g;
+    int rc = check_geo(dtype, nx, ny, nz, &g);
+    if (rc) return rc;
+    if (bc != DCP_DIRICHLET0 && bc != DCP_PERIODIC) return DCP_E_BC;
+    if ((rc = check_coeffs(coeffs))) return rc;
+    if (T < 0 || nslots < 0 || tblock < 1 || tblock > dcp_max_tblock(dtype)) return DCP_E_ARG;
+    if (!grad_ab) return DCP_E_NULL;
+    if (g.n > 0 && (!f || !lam_T || !grad_u0)) return DCP_E_NULL;
+    const bool lsum_field = grad_gamma != nullptr && grad_f == nullptr && g.n > 0;
+    RevWs w;
+    if ((rc = layout_rev(dtype, g, T, nslots, lsum_field, &w))) return rc;
+    if ((rc = check_ws(ws, ws_bytes, w.total))) return rc;
+    const size_t fb = g.bytes();
+    const size_t wsz = w.total;
+    for (const void *p : {f, lam_T})
+        if (overlaps(grad_u0, fb, p, fb) || overlaps(ws, wsz, p, fb) || (grad_f && overlaps(grad_f, fb, p, fb)))
+            return DCP_E_ALIAS;
+    if (overlaps(grad_u0, fb, ws, wsz) || overlaps(grad_ab, 16, ws, wsz) || overlaps(grad_ab, 16, grad_u0, fb))
+        return DCP_E_ALIAS;
+    if (grad_f && (overlaps(grad_f, fb, ws, wsz) || overlaps(grad_f, fb, grad_u0, fb) ||
+                   overlaps(grad_f, fb, grad_ab, 16)))
+        return DCP_E_ALIAS;
+    if (grad_gamma && (overlaps(grad_gamma, 8, grad_ab, 16) || overlaps(grad_gamma, 8, grad_u0, fb) ||
+                       overlaps(grad_gamma, 8, grad_f, grad_f ? fb : 0) || overlaps(grad_gamma, 8, ws, wsz)))
+        return DCP_E_ALIAS;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (T == 0 || g.n == 0) {
+        if (g.n > 0)
+            DCP_TRY(launch_ew(dtype, EW_COPY, lam_T, nullptr, grad_u0, 0.0, g.n,
+                              vec_ok_for(dtype, g, {lam_T, grad_u0}), st));
+        if (grad_f && g.n > 0)
+            DCP_TRY(launch_ew(dtype, EW_ZERO, nullptr, nullptr, grad_f, 0.0, g.n, vec_ok_for(dtype, g, {grad_f}), st));
+        DCP_TRY(launch_zero(grad_ab, 2, st));
+        if (grad_gamma) DCP_TRY(launch_zero(grad_gamma, 1, st));
+        return DCP_OK;
+    }
+    std::vector<RvOp> ops;
+    if (!revolve_schedule(T, nslots, &ops, nullptr)) return DCP_E_ARG;
+    const RevBufs B{ws, &w, nslots, align_up(fb)};
+    void *scratch = at(ws, w.scratch);
+    void *lam[2] = {at(ws, w.lam), at(ws, w.lam + align_up(fb))};
+    void *lsum = grad_f ? grad_f : (lsum_field ? static_cast<void *>(at(ws, w.lsum)) : nullptr);
+    bool vok = vec_ok_for(dtype, g, {f, lam_T, grad_u0, grad_f, B.buf(kRvOrigin), B.buf(nslots), scratch,
+                                     lam[0], lam[1], lsum});
+    for (int32_t i = 0; i < nslots; ++i) vok = vok && aligned16(B.buf(i));
+    const Tile t = pick_tile(dtype, g, vok);
+    TbTile tb{};
+    const bool use_tb = plan_tb(dtype, g, tblock, vok, &tb);
+    const dcp_coeffs &c = *coeffs;
+    double *partials = reinterpret_cast<double *>(at(ws, w.partials));
+    double *sums = reinterpret_cast<double *>(at(ws, w.sums));
+    const int stride = w.nblk;
+    StencilArgs aa{};
+    aa.nx = g.nx;
+    aa.ny = g.ny;
+    aa.nz = g.nz;
+    aa.c0 = c.dt * c.alpha / (c.h * c.h);
+    aa.c1 = 3.0 * c.dt * c.beta;
+    aa.tiles_x = t.tiles_x;
+    aa.tiles_y = t.tiles_y;
+    aa.zc = t.zc;
+    aa.nblk = t.nblk;
+    aa.lam = lsum;
+    const int adj_op = lsum ? SOP_ADJL : SOP_ADJ;
+    int lam_first = 1;
+    const void *lcur = lam_T;
+    // the opening chain of advances was run by dcp_revolve_forward
+    size_t i0 = 0;
+    while (i0 < ops.size() && ops[i0].kind == kRvAdvance) ++i0;
+    for (size_t i = i0; i < ops.size(); ++i) {
+        const RvOp &op = ops[i];
+        if (op.kind == kRvAdvance) {
+            if ((rc = rev_advance(dtype, bc, g, c, t, use_tb, tb, f, B.buf(op.src), B.buf(op.dst), scratch,
+                                  op.t1 - op.t0, st)))
+                return rc;
+            continue;
+        }
+        const int64_t s = op.t0;  // adjoint step s with u_s in buffer op.src
+        void *out = (s == 0) ? grad_u0 : (lcur == lam[0] ? lam[1] : lam[0]);
+        aa.s = lcur;
+        aa.q = B.buf(op.src);
+        aa.out = out;
+        aa.partials = partials + (size_t)s * stride * 2;
+        aa.lam_first = lam_first;
+        DCP_TRY(launch_stencil(dtype, adj_op, bc, true, t, aa, st));
+        lam_first = 0;
+        lcur = out;
+    }
+    DCP_TRY(launch_finalize(partials, t.nblk, stride, T, sums, nullptr, 2, st));
+    DCP_TRY(launch_grad_finalize(sums, T, c.dt / (c.h * c.h), -c.dt, grad_ab, st));
+    if (lsum) {
         if (grad_gamma) {
             double *dp = reinterpret_cast<double *>(at(ws, w.dot));
             const int nb = ew_norm_blocks(g.n);

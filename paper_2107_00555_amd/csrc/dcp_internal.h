@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace dcp {
 
 enum StencilOp : int {
@@ -116,5 +118,19 @@ hipError_t launch_grad_finalize(const double *sums, int nsteps, double s0,
 
 // dst[0..n) = 0 (doubles), a kernel rather than a memset node.
 hipError_t launch_zero(double *dst, int64_t n, hipStream_t stream);
+
+// Binomial checkpointing schedule (dcp_revolve.cpp).  Buffers: kRvOrigin =
+// the saved u_0, 0 .. nslots-1 = snapshot slots, nslots = the work state.
+//   kRvAdvance: state of buffer src (time t0) advanced to time t1 into dst
+//   kRvAdjoint: adjoint step t0 with u_{t0} in buffer src
+// Adjoint steps come in the order T-1, T-2, ..., 0.
+constexpr int kRvOrigin = -1;
+constexpr int kRvAdvance = 0, kRvAdjoint = 1;
+struct RvOp {
+    int kind;
+    int32_t src, dst;
+    int64_t t0, t1;
+};
+bool revolve_schedule(int64_t T, int32_t nslots, std::vector<RvOp> *ops, int64_t *forward_steps);
 
 }  // namespace dcp

@@ -251,3 +251,46 @@ def test_jacobi_plan(L):
     h = ctypes.c_int32(0)
     assert L.lib().dcp_jacobi_plan(2, 10, 1 << 30, 5, 0, ctypes.byref(n), ctypes.byref(h)) == -2
     assert L.lib().dcp_jacobi_plan(2, 10, 10, 5, 0, None, ctypes.byref(h)) == -1
+
+
+# ------------------------------------------------ binomial checkpointing
+def test_revolve_workspace_sizes(L):
+    MiB = 1 << 20
+    fb = 64 * 64 * 64 * 8                       # 2 MiB per field
+    w = L.revolve_workspace_bytes(L.F64, 64, 64, 64, 10, 3)
+    assert 8 * fb <= w < 8 * fb + 4 * MiB       # u0, 3 slots, work, scratch, 2 adjoint fields
+    w2 = L.revolve_workspace_bytes(L.F64, 64, 64, 64, 10, 3, lsum_field=True)
+    assert w2 - w == fb
+    assert L.revolve_workspace_bytes(L.F64, 64, 64, 64, 0, 3) == 0
+    assert L.revolve_workspace_bytes(L.F32, 0, 64, 64, 10, 3) == 0
+
+
+def rev_fwd(L, dtype=0, u=U, f=F, n=(8, 8, 8), bc=0, T=5, s=2, tb=1, ws=WS, wsb=1 << 26):
+    return L.lib().dcp_revolve_forward(dtype, u, f, n[0], n[1], n[2], ctypes.byref(coeffs(L)), bc, T, s, tb,
+                                       ws, wsb, None)
+
+
+def rev_adj(L, dtype=0, f=F, lam=U, n=(8, 8, 8), bc=0, T=5, s=2, tb=1, g=O, gab=0x60000000, gf=None, gg=None,
+            ws=WS, wsb=1 << 26):
+    return L.lib().dcp_revolve_adjoint(dtype, f, lam, n[0], n[1], n[2], ctypes.byref(coeffs(L)), bc, T, s, tb,
+                                       g, gab, gf, gg, ws, wsb, None)
+
+
+def test_revolve_argument_errors(L):
+    assert rev_fwd(L, T=-1) == -5
+    assert rev_fwd(L, s=-1) == -5
+    assert rev_fwd(L, tb=3) == -5
+    assert rev_fwd(L, u=None) == -1
+    assert rev_fwd(L, f=U) == -7
+    assert rev_fwd(L, ws=U + 64) == -7
+    assert rev_fwd(L, wsb=64) == -6
+    assert rev_fwd(L, bc=7) == -4
+    assert rev_fwd(L, dtype=9) == -3
+    assert rev_adj(L, T=-1) == -5
+    assert rev_adj(L, gab=None) == -1
+    assert rev_adj(L, g=None) == -1
+    assert rev_adj(L, g=F) == -7
+    assert rev_adj(L, ws=O + 8) == -7
+    assert rev_adj(L, gf=O) == -7
+    assert rev_adj(L, gf=0x68000000, gg=0x60000008) == -7
+    assert rev_adj(L, wsb=64) == -6

@@ -1,0 +1,131 @@
+"""Binomial checkpointing (dcp_revolve_forward / dcp_revolve_adjoint) on
+the GPU: the forward gives dcp_run's u_T and the reverse sweep
+dcp_adjoint_run's gradients (one adjoint step per pass), bit for bit, for
+any number of slots; against the oracle; gradcheck through RD3D; and at the
+512^3 benchmark grid against checkpoints every 10 steps."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import BASE, DEV, normwise, rand_fields, say, to_dev, to_host
+from paper_2107_00555_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _api():
+    from paper_2107_00555_amd import api
+    return api
+
+
+def both(u0, f, lam, T, bc, nslots, tblock, dtype=torch.float64, k=3):
+    """(revolve u_T, revolve grads, dcp_run u_T, dcp_adjoint_run grads with tblock 1)."""
+    api = _api()
+    fd = to_dev(f, dtype)
+    lam_d = to_dev(lam, dtype)
+    u = to_dev(u0, dtype)
+    ws = api.revolve_forward(u, fd, BASE, T, bc, nslots, tblock=tblock)
+    r = api.revolve_adjoint(ws, fd, lam_d, BASE, T, bc, nslots, tblock=tblock, want_f=True, want_gamma=True)
+    v = to_dev(u0, dtype)
+    out = api.run(v, fd, BASE, T, bc, tblock=tblock, norms=False, ckpt_every=k)
+    ref = api.adjoint_run(out["ckpt"], k, fd, lam_d, BASE, T, bc, tblock=1, want_f=True, want_gamma=True)
+    return u, r, v, ref
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("tblock", [1, 2])
+@pytest.mark.parametrize("bc", [0, 1])
+@pytest.mark.parametrize("T,nslots", [(1, 1), (2, 0), (7, 0), (9, 1), (10, 2), (23, 3), (40, 5), (6, 12)])
+def test_revolve_equals_uniform_checkpoints_bitwise(T, nslots, bc, tblock, dtype):
+    shape = (64, 20, 12)
+    u0, f = rand_fields(shape, 900 + T + nslots)
+    lam = np.random.default_rng(T).uniform(-1, 1, u0.shape)
+    say("revolve", T, nslots, bc, tblock, dtype)
+    u, r, v, ref = both(u0, f, lam, T, bc, nslots, tblock, dtype)
+    assert torch.equal(u, v)
+    for key in ("u0", "ab", "f", "gamma"):
+        assert torch.equal(r[key], ref[key]), key
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_revolve_matches_oracle(bc):
+    shape, T, nslots = (24, 20, 16), 13, 2
+    u0, f = rand_fields(shape, 910)
+    lam = np.random.default_rng(11).uniform(-1, 1, u0.shape)
+    want = oracle.adjoint_full(u0, f, lam, BASE, T, bc)
+    say("revolve vs oracle", bc)
+    _, r, _, _ = both(u0, f, lam, T, bc, nslots, 2)
+    torch.cuda.synchronize()
+    assert normwise(to_host(r["u0"]), want["u0"]) <= 1e-12
+    assert normwise(to_host(r["f"]), want["f"]) <= 1e-12
+    ab = to_host(r["ab"])
+    assert ab[0] == pytest.approx(want["alpha"], rel=1e-11)
+    assert ab[1] == pytest.approx(want["beta"], rel=1e-11)
+    assert float(r["gamma"]) == pytest.approx(want["gamma"], rel=1e-11)
+
+
+def test_revolve_adjoint_needs_a_fresh_forward():
+    """The reverse sweep reuses the slots: a second adjoint call on the same
+    workspace differs, and a second forward restores it."""
+    api = _api()
+    u0, f = rand_fields((32, 16, 8), 914)
+    lam = to_dev(np.random.default_rng(4).uniform(-1, 1, u0.shape))
+    fd = to_dev(f)
+    ws = api.revolve_forward(to_dev(u0), fd, BASE, 20, 0, 2)
+    g1, _ = api.revolve_adjoint(ws, fd, lam, BASE, 20, 0, 2)
+    ws = api.revolve_forward(to_dev(u0), fd, BASE, 20, 0, 2, )
+    g2, _ = api.revolve_adjoint(ws, fd, lam, BASE, 20, 0, 2)
+    assert torch.equal(g1, g2)
+
+
+def test_revolve_zero_steps():
+    api = _api()
+    u0, f = rand_fields((16, 8, 8), 912)
+    u = to_dev(u0)
+    ws = api.revolve_forward(u, to_dev(f), BASE, 0, 1, 3)
+    assert torch.equal(u, to_dev(u0))
+    lam = to_dev(np.random.default_rng(3).uniform(-1, 1, u0.shape))
+    r = api.revolve_adjoint(ws, to_dev(f), lam, BASE, 0, 1, 3, want_f=True, want_gamma=True)
+    torch.cuda.synchronize()
+    assert torch.equal(r["u0"], lam) and torch.count_nonzero(r["f"]) == 0 and float(r["gamma"]) == 0.0
+
+
+def test_gradcheck_through_rd3d_with_revolve():
+    from paper_2107_00555_amd.autograd import rd3d
+    u0, f = rand_fields((6, 5, 4), 913)
+    u = to_dev(u0).requires_grad_(True)
+    fd = to_dev(f).requires_grad_(True)
+    alpha = torch.tensor(1.0, dtype=torch.float64, device=DEV, requires_grad=True)
+    gamma = torch.tensor(0.5, dtype=torch.float64, device=DEV, requires_grad=True)
+    say("gradcheck revolve")
+
+    def fn(u_, f_, a_, g_):
+        return rd3d(u_, f_, a_, 0.1, g_, 0.1, 1.0, 9, "periodic", revolve_slots=2)
+
+    assert torch.autograd.gradcheck(fn, (u, fd, alpha, gamma), eps=1e-6, atol=1e-8, rtol=1e-6)
+
+
+def test_revolve_at_benchmark_grid():
+    """512^3 FP64 periodic, T=100: 4 snapshots against checkpoints every 10
+    steps: the same u_T and dL/du0 bit for bit, the parameter gradients to
+    rounding (the reference pairs its adjoint steps two per pass)."""
+    api = _api()
+    u0_h, f_h = inputs.make_fields("fwd_512_f64", seed=0)
+    T, bc = 100, inputs.PERIODIC
+    fd = to_dev(f_h)
+    u = to_dev(u0_h)
+    say("revolve 512^3 T=100 forward")
+    ws = api.revolve_forward(u, fd, BASE, T, bc, 4)
+    lam = (u - 0.5 * fd).contiguous()
+    say("revolve 512^3 adjoint")
+    r = api.revolve_adjoint(ws, fd, lam, BASE, T, bc, 4)
+    del ws
+    v = to_dev(u0_h)
+    out = api.run(v, fd, BASE, T, bc, norms=False, ckpt_every=10)
+    assert torch.equal(u, v)
+    g, gab = api.adjoint_run(out["ckpt"], 10, fd, lam, BASE, T, bc)
+    torch.cuda.synchronize()
+    assert torch.equal(r[0], g)
+    a, b = to_host(r[1]), to_host(gab)
+    assert a[0] == pytest.approx(b[0], rel=1e-12) and a[1] == pytest.approx(b[1], rel=1e-12)
