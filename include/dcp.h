@@ -327,6 +327,59 @@ int dcp_revolve_adjoint(int dtype, const void *f, const void *lam_T,
 int dcp_revolve_schedule(int64_t T, int32_t nslots, int64_t *ops, int64_t cap,
                          int64_t *nops, int64_t *forward_steps);
 
+/* ---------------------------------------------------------------------------
+ * A fusing compiler for element-wise + stencil programs (the greedy subgraph
+ * fusion and transient elimination of Sec. 3.1, applied to programs in the
+ * single-operator SSA form of Sec. 2.3), generating HIP for gfx950 at run
+ * time.  Program text, one statement per line ('#' starts a comment):
+ *     dtype f64 | f32
+ *     input  NAME ...          fields in memory (nx*ny*nz, x fastest)
+ *     param  NAME ...          scalars given at run time (finite doubles,
+ *                              rounded to the dtype once)
+ *     NAME = add|sub|mul|div A B
+ *     NAME = neg A  |  NAME = copy A
+ *     NAME = shift A dx dy dz  the field A at (x+dx, y+dy, z+dz), under the
+ *                              run's boundary rule (DCP_DIRICHLET0: 0
+ *                              outside; DCP_PERIODIC: indices mod n)
+ *     output NAME ...          fields written to memory
+ * Operands are names defined above or numeric literals.  Every statement is
+ * one map over the grid (a scalar when all its operands are scalars) and
+ * rounds once, so the result equals the statement-by-statement evaluation
+ * bit for bit, fused or not.
+ *
+ * dcp_fuse_build: parses, partitions (fuse = 1: statements go greedily to
+ *   the earliest kernel whose values they can read, a shifted read of a
+ *   computed value starting a new kernel, and only outputs and values read
+ *   by a later kernel are written to memory; fuse = 0: one kernel per
+ *   statement, every value written), generates and compiles the kernels
+ *   (host only; no GPU needed).  On error returns DCP_E_ARG (program text)
+ *   or DCP_E_HIP (compilation) with a message in err (errlen bytes).
+ * dcp_fuse_info: info[0..5] = {dtype, inputs, params, outputs, kernels,
+ *   workspace fields} (the first n of them).
+ * dcp_fuse_source: the generated HIP source (NUL-terminated) into buf of
+ *   len bytes; *needed = its size.
+ * dcp_fuse_workspace_bytes: device workspace for a grid (the values that
+ *   are written to memory but are not outputs).
+ * dcp_fuse_run: inputs[] and outputs[] in declaration order (device
+ *   pointers; outputs must not overlap inputs, each other or ws), params[]
+ *   (host doubles).  Loads the code on the current device at its first run
+ *   there.  A program object is used by one thread at a time.
+ */
+typedef struct dcp_fused dcp_fused;
+
+int dcp_fuse_build(const char *program, int fuse, dcp_fused **out, char *err,
+                   size_t errlen);
+void dcp_fuse_free(dcp_fused *program);
+int dcp_fuse_info(const dcp_fused *program, int32_t *info, int32_t n);
+int dcp_fuse_source(const dcp_fused *program, char *buf, size_t len,
+                    size_t *needed);
+int dcp_fuse_workspace_bytes(const dcp_fused *program, int64_t nx, int64_t ny,
+                             int64_t nz, size_t *bytes);
+int dcp_fuse_run(dcp_fused *program, const void *const *inputs,
+                 const double *params, void *const *outputs, int64_t nx,
+                 int64_t ny, int64_t nz, int bc, void *ws, size_t ws_bytes,
+                 void *stream);
+
 /* Static, NUL-terminated description of a dcp_status value. */
 const char *dcp_status_string(int status);
 

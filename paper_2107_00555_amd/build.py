@@ -33,7 +33,8 @@ COMMON = [
     f"-I{INCLUDE}", f"-I{CSRC}",
 ]
 
-SOURCES = ["dcp_kernels.hip", "dcp_tblock.hip", "dcp_jacobi.hip", "dcp_api.cpp", "dcp_revolve.cpp"]
+SOURCES = ["dcp_kernels.hip", "dcp_tblock.hip", "dcp_jacobi.hip", "dcp_api.cpp", "dcp_revolve.cpp",
+           "dcp_fuse.cpp"]
 
 
 def _compile(src: str) -> str:
@@ -54,7 +55,7 @@ def build(verbose: bool = True) -> str:
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs + ["-lhiprtc"]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     if verbose:

@@ -1,0 +1,99 @@
+"""The fusing compiler on the host (no GPU): program text from the front
+end, the kernel partition and which values reach memory, error reporting,
+and the generated source."""
+import os
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def F():
+    from paper_2107_00555_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2107_00555_amd import build
+        build.build(verbose=False)
+    from paper_2107_00555_amd import fuse
+    return fuse
+
+
+def step_program(F, dtype="f64", h=1.0):
+    P = F.Program(dtype)
+    u, f = P.input("u", "f")
+    alpha, beta, gamma, dt = P.param("alpha", "beta", "gamma", "dt")
+    lap = F.lap7(u, h)
+    u3 = (u * u) * u
+    P.output("unew", u + dt * ((alpha * lap - beta * u3) + gamma * f))
+    return P
+
+
+def test_step_program_fuses_into_one_kernel(F):
+    P = step_program(F)
+    fused = P.compile()
+    assert (fused.n_inputs, fused.n_params, fused.n_outputs) == (2, 4, 1)
+    assert fused.n_kernels == 1 and fused.n_buffers == 0      # no temporary reaches memory
+    assert fused.workspace_bytes((8, 8, 8)) == 0
+    naive = P.compile(fuse=False)
+    assert naive.n_kernels > 15 and naive.n_buffers == naive.n_kernels - 1   # every value but the output
+    assert naive.workspace_bytes((8, 8, 8)) == naive.n_buffers * 8 * 8 * 8 * 8
+
+
+def test_shift_of_a_temporary_starts_a_kernel(F):
+    P = F.Program("f32")
+    u, = P.input("u")
+    t = u * u                       # kernel 0, read shifted later: stored
+    s = t.shift(1, 0, 0)            # kernel 1
+    v = u + 2.0                     # kernel 0, read point-wise by kernel 1: stored
+    P.output("y", s + v)            # kernel 1
+    P.output("z", v * 3.0)          # kernel 0 (its operand is there)
+    fz = P.compile()
+    assert fz.n_kernels == 2 and fz.n_buffers == 2
+    src = fz.source
+    assert "dcp_fused_k0" in src and "dcp_fused_k1" in src and "float" in src
+
+
+def test_chain_of_shifted_temporaries(F):
+    P = F.Program()
+    u, = P.input("u")
+    a = u.shift(1, 0, 0) * 0.5
+    b = a.shift(0, 1, 0) + a
+    c = b.shift(0, 0, -1) - u
+    P.output("c", c)
+    assert P.compile().n_kernels == 3
+
+
+@pytest.mark.parametrize("text,msg", [
+    ("input u\ny = add u u\noutput y\n", "missing dtype"),
+    ("dtype f64\ninput u\ny = add u v\noutput y\n", "undefined"),
+    ("dtype f64\ninput u\ny = add u u\ny = mul u u\noutput y\n", "defined twice"),
+    ("dtype f64\ninput u\nparam p\ny = shift p 1 0 0\noutput y\n", "shift of a scalar"),
+    ("dtype f64\ninput u\ny = pow u u\noutput y\n", "unknown operation"),
+    ("dtype f64\ninput u\ny = add u u\n", "no output"),
+    ("dtype f64\ninput u\noutput u\n", "is an input"),
+    ("dtype f64\ninput u\nparam p\ns = mul p 2\noutput s\n", "scalar"),
+    ("dtype f16\ninput u\n", "dtype"),
+    ("dtype f64\ninput u\ny = shift u 1 x 0\noutput y\n", "bad shift"),
+    ("dtype f64\ninput 9u\n", "bad name"),
+])
+def test_program_errors(F, text, msg):
+    with pytest.raises(F.FuseError, match=msg):
+        F.compile_text(text)
+
+
+def test_literals_are_exact_in_the_source(F):
+    P = F.Program()
+    u, = P.input("u")
+    P.output("y", u * 0.1)
+    src = P.compile().source
+    assert "0x1.999999999999ap-4" in src          # 0.1 as a hex float, exact
+
+
+def test_build_status_codes(F):
+    import ctypes
+    L = F._load()
+    h = ctypes.c_void_p()
+    err = ctypes.create_string_buffer(256)
+    assert L.dcp_fuse_build(None, 1, ctypes.byref(h), err, 256) == -1
+    assert L.dcp_fuse_build(b"dtype f64\n", 1, ctypes.byref(h), err, 256) == -5
+    assert b"no output" in err.value

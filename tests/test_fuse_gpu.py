@@ -1,0 +1,151 @@
+"""Generated kernels of the fusing compiler on the GPU, against the program
+interpreter (oracle/fuse_interp.py): bit for bit, fused and unfused, FP64
+and FP32, both boundary rules; the reaction-diffusion step also against the
+C oracle and the hand-written unfused chain."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import BASE, DEV, rand_fields, say, to_dev, to_host
+from oracle import fuse_interp
+
+pytestmark = pytest.mark.gpu
+
+
+def _fuse():
+    from paper_2107_00555_amd import fuse
+    return fuse
+
+
+def step_program(dtype="f64", h=1.0):
+    F = _fuse()
+    P = F.Program(dtype)
+    u, f = P.input("u", "f")
+    alpha, beta, gamma, dt = P.param("alpha", "beta", "gamma", "dt")
+    lap = F.lap7(u, h)
+    u3 = (u * u) * u
+    t1 = alpha * lap
+    t2 = beta * u3
+    t3 = t1 - t2
+    t4 = gamma * f
+    t5 = t3 + t4
+    t6 = dt * t5
+    P.output("unew", u + t6)
+    return P
+
+
+PARAMS = {k: BASE[k] for k in ("alpha", "beta", "gamma", "dt")}
+
+
+def run_gpu(prog, arrays, params, bc):
+    tdt = prog.dtype
+    outs = prog.run([to_dev(a, tdt) for a in arrays], params, bc=bc)
+    torch.cuda.synchronize()
+    return [o.cpu().numpy() for o in outs]
+
+
+@pytest.mark.parametrize("fuse", [True, False])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("bc", [0, 1])
+@pytest.mark.parametrize("shape", [(37, 19, 23), (1, 1, 1), (64, 3, 5), (2, 2, 9), (130, 66, 4)])
+def test_step_program_matches_interpreter_bitwise(shape, bc, dtype, fuse):
+    P = step_program(dtype)
+    prog = P.compile(fuse)
+    u0, f = rand_fields(shape, 1000 + sum(shape))
+    dt = np.float64 if dtype == "f64" else np.float32
+    u0, f = u0.astype(dt), f.astype(dt)
+    say("fuse step", shape, bc, dtype, fuse)
+    (got,) = run_gpu(prog, [u0, f], PARAMS, bc)
+    (want,) = fuse_interp.run(P.text(), [u0, f], PARAMS, bc)
+    assert got.dtype == want.dtype and np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_ten_generated_steps_equal_c_oracle_and_unfused_chain(bc):
+    from paper_2107_00555_amd import api
+    shape, T = (40, 24, 20), 10
+    prog = step_program("f64").compile()
+    u0, f = rand_fields(shape, 1001)
+    want, _, _ = oracle.run(u0, f, BASE, T, bc, norms=False)
+    u, fd = to_dev(u0), to_dev(f)
+    v = torch.empty_like(u)
+    say("fuse 10 steps", bc)
+    for _ in range(T):
+        prog.run([u, fd], PARAMS, bc=bc, outputs=[v])
+        u, v = v, u
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(u), want)
+    w = to_dev(u0)
+    api.run(w, fd, BASE, T, bc, impl="unfused", norms=False)
+    torch.cuda.synchronize()
+    assert torch.equal(w, u)
+
+
+def random_program(seed, dtype):
+    F = _fuse()
+    rng = np.random.default_rng(seed)
+    P = F.Program(dtype)
+    ins = list(P.input("a", "b", "c"))
+    ps = list(P.param("p", "q"))
+    vals = list(ins)
+    for _ in range(int(rng.integers(8, 30))):
+        k = rng.integers(0, 10)
+        x = vals[int(rng.integers(0, len(vals)))]
+        y = vals[int(rng.integers(0, len(vals)))]
+        s = ps[int(rng.integers(0, 2))] if rng.random() < 0.5 else float(rng.uniform(-2, 2))
+        if k == 0:
+            e = x + y
+        elif k == 1:
+            e = x - s
+        elif k == 2:
+            e = x * y
+        elif k == 3:
+            e = s * x
+        elif k == 4:
+            e = x / (y * y + 1.0)          # never divides by zero
+        elif k == 5:
+            e = -x
+        elif k in (6, 7):
+            e = x.shift(int(rng.integers(-2, 3)), int(rng.integers(-1, 2)), int(rng.integers(-1, 2)))
+        else:
+            e = (x + y) * 0.5
+        vals.append(e)
+    n_out = int(rng.integers(1, 4))
+    for j in range(n_out):
+        P.output(f"o{j}", vals[-1 - 3 * j] if len(vals) > 3 * j + 3 else vals[-1 - j])
+    return P
+
+
+@pytest.mark.parametrize("seed", list(range(12)))
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_random_programs_match_interpreter_bitwise(seed, dtype):
+    P = random_program(seed, dtype)
+    dt = np.float64 if dtype == "f64" else np.float32
+    r = np.random.default_rng(seed + 77)
+    shape = (int(r.integers(1, 50)), int(r.integers(1, 20)), int(r.integers(1, 12)))
+    arrays = [r.uniform(-1, 1, shape).astype(dt) for _ in range(3)]
+    params = {"p": float(r.uniform(-1, 1)), "q": float(r.uniform(-1, 1))}
+    for bc in (0, 1):
+        want = fuse_interp.run(P.text(), arrays, params, bc)
+        for fuse in (True, False):
+            prog = P.compile(fuse)
+            say("fuse random", seed, dtype, shape, bc, fuse, prog.n_kernels)
+            got = run_gpu(prog, arrays, params, bc)
+            for g, w in zip(got, want):
+                assert np.array_equal(g, w), (seed, bc, fuse)
+
+
+def test_run_argument_errors():
+    F = _fuse()
+    from paper_2107_00555_amd import _lib
+    prog = step_program("f64").compile()
+    u = torch.zeros((4, 4, 4), dtype=torch.float64, device=DEV)
+    with pytest.raises(ValueError):
+        prog.run([u], PARAMS)                           # one input short
+    with pytest.raises(ValueError):
+        prog.run([u, u.float()], PARAMS)                # wrong dtype
+    with pytest.raises(_lib.DcpError):
+        prog.run([u, u.clone()], PARAMS, outputs=[u])   # output aliases an input
+    with pytest.raises(_lib.DcpError):
+        prog.run([u, u.clone()], dict(PARAMS, alpha=float("nan")))
