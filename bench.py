@@ -17,8 +17,10 @@ In the same run (--forms all, the default) every other form of the metric
 is timed on the same inputs, each in its own event-timed region: the
 unfused single-operator chain, the float32 forms, the adjoint kernel and
 the end-to-end gradient (forward with checkpoints + checkpointed adjoint);
-then the two Jacobi listings (jacobi_1d, jacobi_2d) at the paper's problem
-sizes and weak-scaled to 1296 processes, with and without temporal blocking.
+one step run by kernels the fusing compiler generates (fused, and one
+kernel per statement) beside the hand-written one-step kernels; then the two
+Jacobi listings (jacobi_1d, jacobi_2d) at the paper's problem sizes and
+weak-scaled to 1296 processes, with and without temporal blocking.
 
 Prints ONE JSON line.  With --gpus N, N > 1, it exits with a message: this
 benchmark runs on one GPU only.
@@ -54,9 +56,9 @@ def parse():
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--seed", type=int, default=0)
-    p.add_argument("--forms", choices=["main", "all", "jacobi"], default="all",
-                   help="main: the headline only; all: every form; jacobi: the Jacobi forms only "
-                        "(no headline line; for profiling)")
+    p.add_argument("--forms", choices=["main", "all", "jacobi", "generated"], default="all",
+                   help="main: the headline only; all: every form; jacobi / generated: the Jacobi "
+                        "forms or the fusing compiler's forms only (no headline line; for profiling)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--jacobi-workloads", default="all",
                    help="comma-separated Jacobi workloads to time (names in inputs.JACOBI_WORKLOADS)")
@@ -197,6 +199,82 @@ def jacobi_forms(args, dev, stream) -> dict:
     return jac
 
 
+def step_program(dtype: str, h: float):
+    """The reaction-diffusion step as a single-operator array program for the
+    fusing compiler (each operator one statement, Python's evaluation order)."""
+    from paper_2107_00555_amd import fuse
+    P = fuse.Program(dtype)
+    u, f = P.input("u", "f")
+    alpha, beta, gamma, dt = P.param("alpha", "beta", "gamma", "dt")
+    lap = fuse.lap7(u, h)
+    P.output("unew", u + dt * ((alpha * lap - beta * ((u * u) * u)) + gamma * f))
+    return P
+
+
+def program_bytes_unfused(text: str, S: int) -> int:
+    """Per-point algorithmic bytes of the unfused program: every field
+    statement reads its field operands and writes its result."""
+    fields = set()
+    total = 0
+    for ln in text.splitlines():
+        t = ln.split()
+        if not t:
+            continue
+        if t[0] == "input":
+            fields.update(t[1:])
+        elif len(t) > 2 and t[1] == "=":
+            ops = t[3:4] if t[2] == "shift" else t[3:]
+            nf = sum(1 for a in ops if a in fields)
+            if nf:
+                fields.add(t[0])
+                total += (nf + 1) * S
+    return total
+
+
+def generated_forms(args, dev, stream, u0, f64, coeffs, bc) -> dict:
+    """One reaction-diffusion step at 512^3 run by kernels the fusing compiler
+    generates (one fused kernel, or one kernel per statement) against the
+    library's hand-written one-step kernels, FP64 and FP32."""
+    import torch
+
+    from paper_2107_00555_amd import api
+    gen = {}
+    N = u0.numel()
+    params = {k: coeffs[k] for k in ("alpha", "beta", "gamma", "dt")}
+    k = max(3, min(args.steps, 10))
+    for dname, tdt, S in (("f64", torch.float64, 8), ("f32", torch.float32, 4)):
+        u = u0.to(tdt)
+        f = f64.to(tdt)
+        out = torch.empty_like(u)
+        P = step_program(dname, coeffs["h"])
+        ent = {}
+        for label, fuse in (("generated_fused", True), ("generated_unfused", False)):
+            prog = P.compile(fuse=fuse)
+            wsb = prog.workspace_bytes(tuple(u.shape))
+            ws = api.workspace(wsb, dev)
+            log(f"timing {label} {dname} ({prog.n_kernels} kernels)")
+            ms, per, _ = timed(lambda: prog.run([u, f], params, bc=bc, outputs=[out], ws=ws), k, 2, stream)
+            ms /= k
+            bpp = 3 * S if fuse else program_bytes_unfused(P.text(), S)
+            ent[label] = {"kernels": prog.n_kernels, "ms": round(ms, 4),
+                          "glups": round(N / (ms * 1e-3) / 1e9, 3),
+                          "bytes_per_point": bpp,
+                          "hbm_frac": round(bpp * N / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            del prog, ws
+        for label, impl in (("handwritten_fused", "fused"), ("handwritten_unfused", "unfused")):
+            log(f"timing {label} {dname}")
+            ms, _, _ = timed(lambda: api.step(u, f, coeffs, bc, impl=impl, out=out), k, 2, stream)
+            ms /= k
+            ent[label] = {"ms": round(ms, 4), "glups": round(N / (ms * 1e-3) / 1e9, 3)}
+        ent["generated_fused_over_unfused"] = round(ent["generated_unfused"]["ms"] / ent["generated_fused"]["ms"], 2)
+        ent["generated_fused_vs_handwritten_fused"] = round(ent["handwritten_fused"]["ms"] /
+                                                             ent["generated_fused"]["ms"], 3)
+        gen[f"step_{dname}"] = ent
+        del u, f, out
+        torch.cuda.empty_cache()
+    return gen
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -227,6 +305,10 @@ def main():
     u0 = torch.from_numpy(u0_h).to(dev)
     f64 = torch.from_numpy(f_h).to(dev)
     u = u0.clone()
+    if args.forms == "generated":
+        print(json.dumps({"forms": {"generated": generated_forms(args, dev, stream, u0, f64, coeffs, bc)},
+                          "data": "synthetic"}), flush=True)
+        return
 
     # ---------------------------------------------------------- headline
     ws = api.workspace(_lib.workspace_bytes(_lib.OP_RUN, _lib.F64, nx, ny, nz, T=T, norms=True,
@@ -447,6 +529,11 @@ def main():
             "vs_checkpoint_every_32": {"ms": round(ms_u1, 1), "forward_steps": 2 * Tr - (Tr + kr - 1) // kr,
                                        "device_memory_gib": round(mem_u / GiB, 2)}}
         del ck, wsf, wsa, g, ug, u32, f32
+
+    # --------------------------------- kernels of the fusing compiler
+    if args.forms == "all":
+        torch.cuda.empty_cache()
+        out["forms"]["generated"] = generated_forms(args, dev, stream, u0, f64, coeffs, bc)
 
     # ------------------------------------------------ the Jacobi listings
     if args.forms == "all":

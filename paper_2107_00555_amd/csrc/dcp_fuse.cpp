@@ -31,7 +31,9 @@
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
+#include <algorithm>
 #include <cctype>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -290,13 +292,29 @@ std::string scalar_expr(const dcp_fused *p, int i, const char *T) {
     return "((" + std::string(T) + ")(" + scalar_expr(p, n.a, T) + op + scalar_expr(p, n.b, T) + "))";
 }
 
+// Generated code.  A lane computes V consecutive x-points (16 bytes of the
+// dtype); a wave covers 64*V consecutive x of one (y, z) row (a wave tile)
+// and walks zr planes; a workgroup takes four consecutive wave tiles.  y and
+// z are uniform over a wave.  The index type is 32-bit when the grid allows
+// it (a second entry point uses 64-bit indices).  Where a plane of a wave
+// tile has its whole y-z stencil footprint inside the grid (a uniform test
+// on the kernel's extreme offsets), a lane reads each operand with one
+// 16-byte vector access at a fixed offset (unaligned for x shifts) unless
+// its V points reach past the row, and then applies the boundary rule per
+// point; elsewhere every point applies the boundary rule.  Points past the
+// row end are computed but not stored.  The V points of a lane are
+// evaluated independently, each statement rounding once, so the results do
+// not depend on V or on the path taken.
 void generate(dcp_fused *p) {
     const char *T = p->dtype == DCP_F64 ? "double" : "float";
+    const int V = p->dtype == DCP_F64 ? 2 : 4;
     std::ostringstream s;
     s << "// generated by dcp_fuse\n"
       << "typedef long long i64;\n"
-      << "template <typename T> __device__ __forceinline__ T dcp_ld(const T *__restrict__ a, i64 x, i64 y, "
-         "i64 z, i64 nx, i64 ny, i64 nz, int bc) {\n"
+      << "#define V " << V << "\n"
+      // one point through the boundary rule (the rare path: kept out of line)
+      << "template <typename T, typename I> __device__ __attribute__((noinline)) T dcp_ld(const T *__restrict__ a, "
+         "I x, I y, I z, I nx, I ny, I nz, int bc) {\n"
       << "    if (x < 0 || x >= nx || y < 0 || y >= ny || z < 0 || z >= nz) {\n"
       << "        if (bc == 0) return T(0);\n"
       << "        x %= nx; if (x < 0) x += nx;\n"
@@ -304,64 +322,296 @@ void generate(dcp_fused *p) {
       << "        z %= nz; if (z < 0) z += nz;\n"
       << "    }\n"
       << "    return a[x + nx * (y + ny * z)];\n"
+      << "}\n"
+      // r = this lane's bit of the wave mask m set ? a : b; taking the
+      // choice from the mask keeps the optimiser from merging the two
+      // sources into one register (which would make a vector load wait)
+      << "__device__ __forceinline__ unsigned dcp_sel32(unsigned long long m, unsigned a, unsigned b) {\n"
+      << "    const unsigned lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));\n"
+      << "    return ((m >> lane) & 1ull) ? a : b;\n"
+      << "}\n"
+      << "__device__ __forceinline__ float dcp_sel(unsigned long long m, float a, float b) {\n"
+      << "    return __builtin_bit_cast(float, dcp_sel32(m, __builtin_bit_cast(unsigned, a), "
+         "__builtin_bit_cast(unsigned, b)));\n"
+      << "}\n"
+      << "__device__ __forceinline__ double dcp_sel(unsigned long long m, double a, double b) {\n"
+      << "    const unsigned long long ua = __builtin_bit_cast(unsigned long long, a), "
+         "ub = __builtin_bit_cast(unsigned long long, b);\n"
+      << "    const unsigned long long lo = dcp_sel32(m, (unsigned)ua, (unsigned)ub);\n"
+      << "    const unsigned long long hi = dcp_sel32(m, (unsigned)(ua >> 32), (unsigned)(ub >> 32));\n"
+      << "    return __builtin_bit_cast(double, (hi << 32) | lo);\n"
+      << "}\n"
+      << "template <typename T> __device__ __forceinline__ void dcp_ldv(const T *__restrict__ a, T *o) {\n"
+      << "    typedef T vt __attribute__((ext_vector_type(V)));\n"
+      << "    vt v;\n"
+      << "    __builtin_memcpy(&v, a, sizeof(vt));\n"
+      << "#pragma unroll\n"
+      << "    for (int j = 0; j < V; ++j) o[j] = v[j];\n"
+      << "}\n"
+      << "template <typename T> __device__ __forceinline__ void dcp_stv(T *__restrict__ a, const T *o) {\n"
+      << "    typedef T vt __attribute__((ext_vector_type(V)));\n"
+      << "    vt v;\n"
+      << "#pragma unroll\n"
+      << "    for (int j = 0; j < V; ++j) v[j] = o[j];\n"
+      << "    __builtin_memcpy(a, &v, sizeof(vt));\n"
+      << "}\n"
+      // V values of one operand: a field read at a fixed offset, through
+      // the boundary rule, or stored only inside the grid
+      // inside the y-z footprint a read is one vector load of V values of
+      // the row at a start clamped into the row (dcp_vidx); a lane whose
+      // points reach past the row then takes its values through the
+      // boundary rule instead (dcp_fix, into other registers)
+      << "template <typename I> __device__ __forceinline__ I dcp_vidx(bool inner, I i, I x, I dx, I dy, I dz, I nx, "
+         "I ny) {\n"
+      << "    const I xs = x + dx;\n"
+      << "    const I xc = xs < 0 ? (I)0 : (xs + V > nx ? nx - V : xs);\n"
+      << "    return i + (xc - x) + (inner ? nx * (dy + ny * dz) : (I)0);\n"
+      << "}\n"
+      // the values a lane's vector load cannot give, into f: inside the y-z
+      // footprint only x leaves the row, by less than one row length, so it
+      // wraps (or the value is zero); elsewhere the boundary rule per point
+      << "template <typename T, typename I> __device__ __forceinline__ void dcp_fixld(const T *__restrict__ a, "
+         "T *f, bool inner, I i, I x, I dx, I dy, I dz, I y, I z, I nx, I ny, I nz, int bc) {\n"
+      << "    if (inner) {\n"
+      << "        if (x + dx < 0 || x + dx + V > nx) {\n"
+      << "            const I row = i - x + nx * (dy + ny * dz);\n"
+      << "#pragma unroll\n"
+      << "            for (int j = 0; j < V; ++j) {\n"
+      << "                const I xj = x + j + dx;\n"
+      << "                const I xw = xj < 0 ? xj + nx : (xj >= nx ? xj - nx : xj);\n"
+      << "                if (bc != 0 || xw == xj) f[j] = a[row + xw];\n"
+      << "            }\n"
+      << "        }\n"
+      << "    } else {\n"
+      << "#pragma unroll\n"
+      << "        for (int j = 0; j < V; ++j) f[j] = dcp_ld<T, I>(a, x + j + dx, y + dy, z + dz, nx, ny, nz, bc);\n"
+      << "    }\n"
+      << "}\n"
+      // a lane takes its vector load where it covers the lane's V points
+      << "template <typename T, typename I> __device__ __forceinline__ void dcp_pick(const T *q, const T *f, T *o, "
+         "bool inner, I x, I dx, I nx) {\n"
+      << "    const unsigned long long m = __builtin_amdgcn_ballot_w64(inner && x + dx >= 0 && x + dx + V <= nx);\n"
+      << "#pragma unroll\n"
+      << "    for (int j = 0; j < V; ++j) o[j] = dcp_sel(m, q[j], f[j]);\n"
+      << "}\n"
+      << "template <typename T, typename I> __device__ __forceinline__ void dcp_wr(T *__restrict__ a, "
+         "const T *o, I i, I x, I nx) {\n"
+      << "    if (x + V <= nx) { dcp_stv<T>(a + i, o); return; }\n"
+      << "#pragma unroll\n"
+      << "    for (int j = 0; j < V; ++j)\n"
+      << "        if (x + j < nx) a[i + j] = o[j];\n"
       << "}\n";
     for (size_t k = 0; k < p->kernels.size(); ++k) {
         const Kernel &K = p->kernels[k];
-        s << "extern \"C\" __global__ void __launch_bounds__(256) " << K.fname << "(";
+        // extreme offsets of this kernel's shifted reads
+        int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+        for (int i : K.nodes) {
+            const Node &n = p->nodes[i];
+            if (n.kind != K_SHIFT) continue;
+            const int d[3] = {n.dx, n.dy, n.dz};
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = std::min(lo[a], d[a]);
+                hi[a] = std::max(hi[a], d[a]);
+            }
+        }
+        std::ostringstream params_decl, params_pass;
         bool first = true;
-        auto sep = [&]() { s << (first ? "" : ", "); first = false; };
+        auto sep = [&]() {
+            if (!first) {
+                params_decl << ", ";
+                params_pass << ", ";
+            }
+            first = false;
+        };
         for (int r : K.reads) {
             sep();
-            s << "const " << T << " *__restrict__ m" << r;
+            params_decl << "const " << T << " *__restrict__ m" << r;
+            params_pass << "m" << r;
         }
         for (int w : K.writes) {
             sep();
-            s << T << " *__restrict__ w" << w;
+            params_decl << T << " *__restrict__ w" << w;
+            params_pass << "w" << w;
         }
         for (size_t j = 0; j < p->params.size(); ++j) {
             sep();
-            s << "double p" << j;
+            params_decl << "double p" << j;
+            params_pass << "p" << j;
         }
         sep();
-        s << "i64 nx, i64 ny, i64 nz, int bc) {\n";
-        s << "    const i64 n = nx * ny * nz;\n"
-          << "    for (i64 i = (i64)blockIdx.x * 256 + threadIdx.x; i < n; i += (i64)gridDim.x * 256) {\n"
-          << "        const i64 x = i % nx, yz = i / nx, y = yz % ny, z = yz / ny;\n"
-          << "        (void)x; (void)y; (void)z;\n";
-        // memory operands read point-wise, loaded once
+        params_decl << "i64 nx_, i64 ny_, i64 nz_, int bc";
+        params_pass << "nx_, ny_, nz_, bc";
+        // the kernel's memory reads, in program order (reads have no side
+        // effects, so they all go first)
+        struct Rd {
+            std::string dst, src;
+            int dx, dy, dz;
+        };
+        std::vector<Rd> rds;
         std::vector<char> loaded(p->nodes.size(), 0);
+        for (int i : K.nodes) {
+            const Node &n = p->nodes[i];
+            if (n.kind == K_SHIFT) {
+                rds.push_back(Rd{"v" + std::to_string(i), "m" + std::to_string(n.a), n.dx, n.dy, n.dz});
+                continue;
+            }
+            for (int o : {n.a, n.b}) {
+                if (o < 0) continue;
+                const Node &m = p->nodes[o];
+                if (!m.field || loaded[o] || !(m.kind == K_INPUT || m.kernel != (int)k)) continue;
+                rds.push_back(Rd{"r" + std::to_string(o), "m" + std::to_string(o), 0, 0, 0});
+                loaded[o] = 1;
+            }
+        }
+        auto offs = [](const Rd &r) {
+            return "(I)(" + std::to_string(r.dx) + "), (I)(" + std::to_string(r.dy) + "), (I)(" +
+                   std::to_string(r.dz) + ")";
+        };
+        std::ostringstream qdecl, fdecl, qpass_a, qpass_b, fpass;
+        for (size_t j = 0; j < rds.size(); ++j) {
+            qdecl << ", " << T << " *q" << j;
+            fdecl << ", " << T << " *f" << j;
+            qpass_a << ", qa" << j;
+            qpass_b << ", qb" << j;
+            fpass << ", fx" << j;
+        }
+        // one plane's vector loads; outside the y-z footprint they read the
+        // lane's own row instead (the values are not used), so the loads are
+        // issued on every path
+        s << "template <typename I> __device__ __forceinline__ void " << K.fname << "_issue("
+          << params_decl.str() << ", bool inner, I i, I x, I nx, I ny" << qdecl.str() << ") {\n";
+        for (size_t j = 0; j < rds.size(); ++j)
+            s << "    dcp_ldv<" << T << ">(" << rds[j].src << " + dcp_vidx<I>(inner, i, x, " << offs(rds[j])
+              << ", nx, ny), q" << j << ");\n";
+        s << "}\n";
+        // one plane's row-end and boundary reads
+        s << "template <typename I> __device__ __forceinline__ void " << K.fname << "_fix(" << params_decl.str()
+          << ", bool inner, I x, I y, I z, I i, I nx, I ny, I nz" << fdecl.str() << ") {\n";
+        for (size_t j = 0; j < rds.size(); ++j)
+            s << "#pragma unroll\n"
+              << "    for (int j = 0; j < V; ++j) f" << j << "[j] = " << T << "(0);\n"
+              << "    dcp_fixld<" << T << ", I>(" << rds[j].src << ", f" << j << ", inner, i, x, " << offs(rds[j])
+              << ", y, z, nx, ny, nz, bc);\n";
+        s << "}\n";
+        // the rest of one plane: the choice per lane, the statements and the
+        // stores
+        s << "template <typename I> __device__ __forceinline__ void " << K.fname << "_done(" << params_decl.str()
+          << ", bool inner, I x, I y, I z, I i, I nx, I ny, I nz" << qdecl.str() << fdecl.str() << ") {\n";
+        for (size_t j = 0; j < rds.size(); ++j) s << "    " << T << " " << rds[j].dst << "[V];\n";
+        for (size_t j = 0; j < rds.size(); ++j)
+            s << "    dcp_pick<" << T << ", I>(q" << j << ", f" << j << ", " << rds[j].dst << ", inner, x, (I)("
+              << rds[j].dx << "), nx);\n";
+        // operand o for point j
         auto val = [&](int o) -> std::string {
             const Node &m = p->nodes[o];
             if (!m.field) return scalar_expr(p, o, T);
-            const bool mem = m.kind == K_INPUT || m.kernel != (int)k;
-            if (mem) {
-                if (!loaded[o]) {
-                    s << "        const " << T << " r" << o << " = m" << o << "[i];\n";
-                    loaded[o] = 1;
-                }
-                return "r" + std::to_string(o);
-            }
-            return "v" + std::to_string(o);
+            if (m.kind == K_INPUT || m.kernel != (int)k) return "r" + std::to_string(o) + "[j]";
+            return "v" + std::to_string(o) + "[j]";
         };
         for (int i : K.nodes) {
             const Node &n = p->nodes[i];
-            std::string e;
-            if (n.kind == K_SHIFT) {
-                e = "dcp_ld<" + std::string(T) + ">(m" + std::to_string(n.a) + ", x + (" + std::to_string(n.dx) +
-                    "), y + (" + std::to_string(n.dy) + "), z + (" + std::to_string(n.dz) + "), nx, ny, nz, bc)";
-            } else if (n.kind == K_NEG) {
-                e = "-" + val(n.a);
-            } else if (n.kind == K_COPY) {
-                e = val(n.a);
-            } else {
-                const std::string a = val(n.a), b = val(n.b);
-                const char *op = n.kind == K_ADD ? " + " : n.kind == K_SUB ? " - " : n.kind == K_MUL ? " * " : " / ";
-                e = a + op + b;
+            if (n.kind != K_SHIFT) {
+                std::string e;
+                if (n.kind == K_NEG) {
+                    e = "-" + val(n.a);
+                } else if (n.kind == K_COPY) {
+                    e = val(n.a);
+                } else {
+                    const std::string a = val(n.a), b = val(n.b);
+                    const char *op =
+                        n.kind == K_ADD ? " + " : n.kind == K_SUB ? " - " : n.kind == K_MUL ? " * " : " / ";
+                    e = a + op + b;
+                }
+                s << "    " << T << " v" << i << "[V];\n"
+                  << "#pragma unroll\n"
+                  << "    for (int j = 0; j < V; ++j) v" << i << "[j] = " << e << ";\n";
             }
-            s << "        const " << T << " v" << i << " = " << e << ";\n";
-            if (n.stored) s << "        w" << i << "[i] = v" << i << ";\n";
+            if (n.stored) s << "    dcp_wr<" << T << ", I>(w" << i << ", v" << i << ", i, x, nx);\n";
         }
-        s << "    }\n}\n";
+        s << "}\n";
+        for (const char *suffix : {"_i32", "_i64"}) {
+            const char *I = suffix[2] == '3' ? "int" : "i64";
+            auto issue = [&](const std::string &inn, const std::string &idx, const std::ostringstream &qp) {
+                return K.fname + "_issue<I>(" + params_pass.str() + ", " + inn + ", " + idx + ", x, nx, ny" +
+                       qp.str() + ")";
+            };
+            auto fix = [&](const std::string &inn, const std::string &z, const std::string &idx) {
+                return K.fname + "_fix<I>(" + params_pass.str() + ", " + inn + ", x, y, " + z + ", " + idx +
+                       ", nx, ny, nz" + fpass.str() + ")";
+            };
+            auto done = [&](const std::string &inn, const std::string &z, const std::string &idx,
+                            const std::ostringstream &qp) {
+                return K.fname + "_done<I>(" + params_pass.str() + ", " + inn + ", x, y, " + z + ", " + idx +
+                       ", nx, ny, nz" + qp.str() + fpass.str() + ")";
+            };
+            std::ostringstream qsets;
+            for (size_t j = 0; j < rds.size(); ++j)
+                qsets << "        " << T << " qa" << j << "[V], qb" << j << "[V], fx" << j << "[V];\n"
+                      << "#pragma unroll\n"
+                      << "        for (int j = 0; j < V; ++j) { qa" << j << "[j] = " << T << "(0); qb" << j
+                      << "[j] = " << T << "(0); }\n";
+            const std::string zin = "iny && (zz) + (" + std::to_string(lo[2]) + ") >= 0 && (zz) + (" +
+                                    std::to_string(hi[2]) + ") < nz";
+            auto zin_at = [&](const std::string &zz) {
+                std::string r = zin;
+                for (size_t pos; (pos = r.find("zz")) != std::string::npos;) r.replace(pos, 2, zz);
+                return r;
+            };
+            s << "extern \"C\" __global__ void __launch_bounds__(256) " << K.fname << suffix << "("
+              << params_decl.str() << ", int zr, i64 tiles_x_, i64 nchunk_) {\n"
+              << "    typedef " << I << " I;\n"
+              << "    const I nx = (I)nx_, ny = (I)ny_, nz = (I)nz_, tiles_x = (I)tiles_x_;\n"
+              << "    const I nb = tiles_x * ny * (I)nchunk_, nwg = (nb + 3) / 4;\n"
+              << "    const I G = (I)gridDim.x, b = (I)blockIdx.x;\n"
+              // workgroups go to the 8 XCDs in turn: give each XCD one
+              // contiguous range of tiles so row neighbours share its L2
+              << "    const I xcd = b % 8, k = b / 8, q = G / 8, r = G % 8;\n"
+              << "    const I lb = xcd < r ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;\n"
+              << "    const I wv = (I)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));\n"
+              << "    const I lane = (I)(threadIdx.x & 63);\n"
+              << "    const I plane = nx * ny;\n"
+              << "    for (I L = lb; L < nwg; L += G) {\n"
+              << "        const I wt = L * 4 + wv;\n"
+              << "        if (wt >= nb) continue;\n"
+              << "        const I xt = wt % tiles_x, t = wt / tiles_x, y = t % ny, zb = (t / ny) * (I)zr;\n"
+              << "        const I x = xt * " << 64 * V << " + lane * V;\n"
+              << "        if (x >= nx) continue;\n"
+              << "        const bool iny = y + (" << lo[1] << ") >= 0 && y + (" << hi[1] << ") < ny;\n"
+              << "        const I ze = (zb + (I)zr < nz ? zb + (I)zr : nz);\n"
+              << "        I i = x + nx * y + plane * zb;\n"
+              // two register sets: the next plane's vector loads are in
+              // flight while this plane is finished
+              << qsets.str()
+              // rows shorter than V points plus the largest x offset: every
+              // point through the boundary rule
+              << "        if (nx < V + " << std::max(-lo[0], hi[0]) << ") {\n"
+              << "            for (I z = zb; z < ze; ++z, i += plane) {\n"
+              << "                " << fix("false", "z", "i") << ";\n"
+              << "                " << done("false", "z", "i", qpass_a) << ";\n"
+              << "            }\n"
+              << "            continue;\n"
+              << "        }\n"
+              // loads complete in order: a plane's row-end reads go out
+              // before the next plane's vector loads, so waiting for the
+              // former does not wait for the latter; the next plane's loads
+              // go out on every path (past the chunk's end they re-read
+              // this row, unused)
+              << "        bool ia = " << zin_at("zb") << ", ib = false;\n"
+              << "        " << issue("ia", "i", qpass_a) << ";\n"
+              << "        for (I z = zb; z < ze; z += 2, i += 2 * plane) {\n"
+              << "            " << fix("ia", "z", "i") << ";\n"
+              << "            ib = z + 1 < ze && " << zin_at("z + 1") << ";\n"
+              << "            " << issue("ib", "(z + 1 < ze ? i + plane : i)", qpass_b) << ";\n"
+              << "            " << done("ia", "z", "i", qpass_a) << ";\n"
+              << "            if (z + 1 >= ze) break;\n"
+              << "            " << fix("ib", "z + 1", "i + plane") << ";\n"
+              << "            ia = z + 2 < ze && " << zin_at("z + 2") << ";\n"
+              << "            " << issue("ia", "(z + 2 < ze ? i + 2 * plane : i)", qpass_a) << ";\n"
+              << "            " << done("ib", "z + 1", "i + plane", qpass_b) << ";\n"
+              << "        }\n"
+              << "    }\n"
+              << "}\n";
+        }
     }
     p->source = s.str();
 }
@@ -496,14 +746,16 @@ int dcp_fuse_run(dcp_fused *p, const void *const *inputs, const double *params, 
     if (it == p->modules.end()) {
         hipModule_t m;
         if (hipModuleLoadData(&m, p->code.data()) != hipSuccess) return DCP_E_HIP;
-        std::vector<hipFunction_t> fns;
+        std::vector<hipFunction_t> fns;  // per kernel: 32-bit, then 64-bit indices
         for (const Kernel &K : p->kernels) {
-            hipFunction_t f;
-            if (hipModuleGetFunction(&f, m, K.fname.c_str()) != hipSuccess) {
-                hipModuleUnload(m);
-                return DCP_E_HIP;
+            for (const char *suffix : {"_i32", "_i64"}) {
+                hipFunction_t f;
+                if (hipModuleGetFunction(&f, m, (K.fname + suffix).c_str()) != hipSuccess) {
+                    hipModuleUnload(m);
+                    return DCP_E_HIP;
+                }
+                fns.push_back(f);
             }
-            fns.push_back(f);
         }
         it = p->modules.emplace(dev, std::make_pair(m, fns)).first;
     }
@@ -513,8 +765,31 @@ int dcp_fuse_run(dcp_fused *p, const void *const *inputs, const double *params, 
         if (m.out >= 0) return outputs[m.out];
         return static_cast<char *>(ws) + (size_t)m.buf * align256(fb);
     };
-    const int64_t blocks64 = std::min<int64_t>((n + 255) / 256, 1 << 16);
-    const unsigned blocks = (unsigned)std::max<int64_t>(blocks64, 1);
+    // wave tiles: 64*V x-points of one row (V points per lane, 16 bytes) over
+    // zr consecutive planes, ordered x tile, then row, then plane chunk; four
+    // per workgroup; a one-dimensional grid of at most 2^20 workgroups
+    // strides over them.  zr doubles, up to 16, while at least 4096
+    // workgroups (16 per CU) remain.
+    const int64_t tile_w = p->dtype == DCP_F64 ? 128 : 256;
+    int64_t tiles_x = (nx + tile_w - 1) / tile_w;
+    int64_t zr = 1;
+    while (zr < 16 && tiles_x * ny * ((nz + 2 * zr - 1) / (2 * zr)) >= 4 * 4096) zr *= 2;
+    int64_t nchunk = (nz + zr - 1) / zr;
+    const unsigned grid = (unsigned)std::min<int64_t>((tiles_x * ny * nchunk + 3) / 4, 1 << 20);
+    int zr32 = (int)zr;
+    double smax[3] = {0, 0, 0};  // largest |offset| of any shifted read, per axis
+    for (const Node &m : p->nodes)
+        if (m.kind == K_SHIFT) {
+            smax[0] = std::max(smax[0], (double)std::abs(m.dx));
+            smax[1] = std::max(smax[1], (double)std::abs(m.dy));
+            smax[2] = std::max(smax[2], (double)std::abs(m.dz));
+        }
+    // every 32-bit intermediate (a point's index, an offset neighbour's
+    // index, a coordinate plus an offset, a tile start rounded up to 256, a
+    // row or chunk start one grid stride past the end) is bounded by this sum
+    const bool idx32 = 2.0 * (double)n + smax[0] + (double)nx * (smax[1] + (double)ny * smax[2]) +
+                           (double)(1 << 21) <
+                       (double)INT32_MAX;
     hipStream_t st = static_cast<hipStream_t>(stream);
     for (size_t k = 0; k < p->kernels.size(); ++k) {
         const Kernel &K = p->kernels[k];
@@ -529,8 +804,12 @@ int dcp_fuse_run(dcp_fused *p, const void *const *inputs, const double *params, 
         for (auto &v : pv) args.push_back(&v);
         for (auto &d : dims) args.push_back(&d);
         args.push_back(&bcv);
-        if (hipModuleLaunchKernel(it->second.second[k], blocks, 1, 1, 256, 1, 1, 0, st, args.data(), nullptr) !=
-            hipSuccess)
+        args.push_back(&zr32);
+        args.push_back(&tiles_x);
+        args.push_back(&nchunk);
+        hipFunction_t fn = it->second.second[2 * k + (idx32 ? 0 : 1)];
+        if (hipModuleLaunchKernel(fn, grid, 1, 1, 256, 1, 1, 0, st, args.data(),
+                                  nullptr) != hipSuccess)
             return DCP_E_HIP;
     }
     return DCP_OK;

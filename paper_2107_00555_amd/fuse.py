@@ -160,9 +160,13 @@ class Fused:
         self.params = [p for group in self.params for p in group]
 
     def __del__(self):
-        if getattr(self, "_h", None):
-            _load().dcp_fuse_free(self._h)
-            self._h = None
+        h = getattr(self, "_h", None)
+        self._h = None
+        if h:
+            try:
+                _load().dcp_fuse_free(h)
+            except Exception:        # interpreter shutdown: the library is gone
+                pass
 
     @property
     def source(self) -> str:

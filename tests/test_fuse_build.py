@@ -97,3 +97,20 @@ def test_build_status_codes(F):
     assert L.dcp_fuse_build(None, 1, ctypes.byref(h), err, 256) == -1
     assert L.dcp_fuse_build(b"dtype f64\n", 1, ctypes.byref(h), err, 256) == -5
     assert b"no output" in err.value
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_random_programs_compile_with_torch_loaded(F, seed, dtype):
+    # run-time compilation goes through whichever device compiler the process
+    # has loaded; with torch imported first that is torch's own, which must
+    # accept every generated construct (an inline-asm select crashed it)
+    import sys
+    import torch  # noqa: F401
+    assert "torch" in sys.modules
+    from fuse_programs import random_program
+    P = random_program(seed, dtype)
+    for fuse in (True, False):
+        prog = P.compile(fuse)
+        assert prog.n_kernels >= 1
+        assert "asm" not in prog.source

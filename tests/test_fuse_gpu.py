@@ -7,6 +7,7 @@ import pytest
 import torch
 
 import oracle
+from fuse_programs import random_program
 from gpu_util import BASE, DEV, rand_fields, say, to_dev, to_host
 from oracle import fuse_interp
 
@@ -48,7 +49,13 @@ def run_gpu(prog, arrays, params, bc):
 @pytest.mark.parametrize("fuse", [True, False])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("bc", [0, 1])
-@pytest.mark.parametrize("shape", [(37, 19, 23), (1, 1, 1), (64, 3, 5), (2, 2, 9), (130, 66, 4)])
+@pytest.mark.parametrize("shape", [(37, 19, 23), (1, 1, 1), (64, 3, 5), (2, 2, 9), (130, 66, 4),
+                                   # (nx, ny, nz): three x tiles of 256 lanes (512 points in
+                                   # float64, 1024 in float32) with interior tiles, a ragged last
+                                   # tile, and a row length that is not a multiple of 4
+                                   (2150, 4, 5), (3073, 3, 3),
+                                   # more rows than the grid's y extent; more z chunks than its z extent
+                                   (3, 70000, 2), (1, 1, 1100000)])
 def test_step_program_matches_interpreter_bitwise(shape, bc, dtype, fuse):
     P = step_program(dtype)
     prog = P.compile(fuse)
@@ -82,41 +89,6 @@ def test_ten_generated_steps_equal_c_oracle_and_unfused_chain(bc):
     assert torch.equal(w, u)
 
 
-def random_program(seed, dtype):
-    F = _fuse()
-    rng = np.random.default_rng(seed)
-    P = F.Program(dtype)
-    ins = list(P.input("a", "b", "c"))
-    ps = list(P.param("p", "q"))
-    vals = list(ins)
-    for _ in range(int(rng.integers(8, 30))):
-        k = rng.integers(0, 10)
-        x = vals[int(rng.integers(0, len(vals)))]
-        y = vals[int(rng.integers(0, len(vals)))]
-        s = ps[int(rng.integers(0, 2))] if rng.random() < 0.5 else float(rng.uniform(-2, 2))
-        if k == 0:
-            e = x + y
-        elif k == 1:
-            e = x - s
-        elif k == 2:
-            e = x * y
-        elif k == 3:
-            e = s * x
-        elif k == 4:
-            e = x / (y * y + 1.0)          # never divides by zero
-        elif k == 5:
-            e = -x
-        elif k in (6, 7):
-            e = x.shift(int(rng.integers(-2, 3)), int(rng.integers(-1, 2)), int(rng.integers(-1, 2)))
-        else:
-            e = (x + y) * 0.5
-        vals.append(e)
-    n_out = int(rng.integers(1, 4))
-    for j in range(n_out):
-        P.output(f"o{j}", vals[-1 - 3 * j] if len(vals) > 3 * j + 3 else vals[-1 - j])
-    return P
-
-
 @pytest.mark.parametrize("seed", list(range(12)))
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_random_programs_match_interpreter_bitwise(seed, dtype):
@@ -131,6 +103,27 @@ def test_random_programs_match_interpreter_bitwise(seed, dtype):
         for fuse in (True, False):
             prog = P.compile(fuse)
             say("fuse random", seed, dtype, shape, bc, fuse, prog.n_kernels)
+            got = run_gpu(prog, arrays, params, bc)
+            for g, w in zip(got, want):
+                assert np.array_equal(g, w), (seed, bc, fuse)
+
+
+@pytest.mark.parametrize("seed", [3, 5, 8, 11])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_random_programs_wide_grid_bitwise(seed, dtype):
+    # rows of several tiles: interior workgroups take the vector reads at
+    # fixed offsets, edge and ragged workgroups the boundary rule
+    P = random_program(seed, dtype)
+    r = np.random.default_rng(seed + 99)
+    shape = (5, 4, 2301)
+    dt = np.float64 if dtype == "f64" else np.float32
+    arrays = [r.uniform(-1, 1, shape).astype(dt) for _ in range(3)]
+    params = {"p": float(r.uniform(-1, 1)), "q": float(r.uniform(-1, 1))}
+    for bc in (0, 1):
+        want = fuse_interp.run(P.text(), arrays, params, bc)
+        for fuse in (True, False):
+            prog = P.compile(fuse)
+            say("fuse random wide", seed, dtype, shape, bc, fuse, prog.n_kernels)
             got = run_gpu(prog, arrays, params, bc)
             for g, w in zip(got, want):
                 assert np.array_equal(g, w), (seed, bc, fuse)
