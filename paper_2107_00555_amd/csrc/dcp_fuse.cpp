@@ -296,15 +296,22 @@ std::string scalar_expr(const dcp_fused *p, int i, const char *T) {
 // dtype); a wave covers 64*V consecutive x of one (y, z) row (a wave tile)
 // and walks zr planes; a workgroup takes four consecutive wave tiles.  y and
 // z are uniform over a wave.  The index type is 32-bit when the grid allows
-// it (a second entry point uses 64-bit indices).  Where a plane of a wave
-// tile has its whole y-z stencil footprint inside the grid (a uniform test
-// on the kernel's extreme offsets), a lane reads each operand with one
-// 16-byte vector access at a fixed offset (unaligned for x shifts) unless
-// its V points reach past the row, and then applies the boundary rule per
-// point; elsewhere every point applies the boundary rule.  Points past the
-// row end are computed but not stored.  The V points of a lane are
-// evaluated independently, each statement rounding once, so the results do
-// not depend on V or on the path taken.
+// it (a second entry point uses 64-bit indices).
+//
+// Reads of a memory field are grouped by (field, dy).  A group keeps, in
+// registers, one aligned V-wide vector of the lane's own x-points for each
+// plane z+dz its reads need (a queue that moves up one plane per step), so
+// a plane costs one vector load per group, issued one plane ahead.  y and z
+// wrap; under the ghost-zero rule a slot outside the grid reads as zero.  A
+// read shifted by |dx| <= V takes its values from the lane's own vector and
+// the neighbouring lane's (cross-lane moves).  Lanes whose values would come
+// from outside the wave tile or the row (the first lane for dx < 0, the last
+// lanes for dx > 0, the lane at a ragged row end), and every lane of a read
+// with |dx| > V, take them per point through the boundary rule instead.
+// Grids too small for one wrap per axis take every point through the rule.
+// Points past the row end are computed but not stored.  The V points of a
+// lane are evaluated independently, each statement rounding once, so the
+// results do not depend on V or on the path taken.
 void generate(dcp_fused *p) {
     const char *T = p->dtype == DCP_F64 ? "double" : "float";
     const int V = p->dtype == DCP_F64 ? 2 : 4;
@@ -312,7 +319,7 @@ void generate(dcp_fused *p) {
     s << "// generated by dcp_fuse\n"
       << "typedef long long i64;\n"
       << "#define V " << V << "\n"
-      // one point through the boundary rule (the rare path: kept out of line)
+      // one point through the boundary rule (the small-grid path: out of line)
       << "template <typename T, typename I> __device__ __attribute__((noinline)) T dcp_ld(const T *__restrict__ a, "
          "I x, I y, I z, I nx, I ny, I nz, int bc) {\n"
       << "    if (x < 0 || x >= nx || y < 0 || y >= ny || z < 0 || z >= nz) {\n"
@@ -323,6 +330,10 @@ void generate(dcp_fused *p) {
       << "    }\n"
       << "    return a[x + nx * (y + ny * z)];\n"
       << "}\n"
+      << "template <typename I> __device__ __forceinline__ I dcp_wrap(I c, I n) {\n"
+      << "    return c < 0 ? c + n : (c >= n ? c - n : c);\n"
+      << "}\n"
+      << "template <typename I> __device__ __forceinline__ bool dcp_in(I c, I n) { return c >= 0 && c < n; }\n"
       // r = this lane's bit of the wave mask m set ? a : b; taking the
       // choice from the mask keeps the optimiser from merging the two
       // sources into one register (which would make a vector load wait)
@@ -341,6 +352,20 @@ void generate(dcp_fused *p) {
       << "    const unsigned long long hi = dcp_sel32(m, (unsigned)(ua >> 32), (unsigned)(ub >> 32));\n"
       << "    return __builtin_bit_cast(double, (hi << 32) | lo);\n"
       << "}\n"
+      // the value of lane - 1 (lower) or lane + 1 (upper); zero at the wave's
+      // ends and from inactive lanes
+      << "template <int CTRL> __device__ __forceinline__ float dcp_dpp(float v) {\n"
+      << "    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, "
+         "true));\n"
+      << "}\n"
+      << "template <int CTRL> __device__ __forceinline__ double dcp_dpp(double v) {\n"
+      << "    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);\n"
+      << "    const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, true);\n"
+      << "    const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, true);\n"
+      << "    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);\n"
+      << "}\n"
+      << "#define DCP_LOWER 0x138\n"  // wave_shr:1
+      << "#define DCP_UPPER 0x130\n"  // wave_shl:1
       << "template <typename T> __device__ __forceinline__ void dcp_ldv(const T *__restrict__ a, T *o) {\n"
       << "    typedef T vt __attribute__((ext_vector_type(V)));\n"
       << "    vt v;\n"
@@ -355,65 +380,34 @@ void generate(dcp_fused *p) {
       << "    for (int j = 0; j < V; ++j) v[j] = o[j];\n"
       << "    __builtin_memcpy(a, &v, sizeof(vt));\n"
       << "}\n"
-      // V values of one operand: a field read at a fixed offset, through
-      // the boundary rule, or stored only inside the grid
-      // inside the y-z footprint a read is one vector load of V values of
-      // the row at a start clamped into the row (dcp_vidx); a lane whose
-      // points reach past the row then takes its values through the
-      // boundary rule instead (dcp_fix, into other registers)
-      << "template <typename I> __device__ __forceinline__ I dcp_vidx(bool inner, I i, I x, I dx, I dy, I dz, I nx, "
-         "I ny) {\n"
-      << "    const I xs = x + dx;\n"
-      << "    const I xc = xs < 0 ? (I)0 : (xs + V > nx ? nx - V : xs);\n"
-      << "    return i + (xc - x) + (inner ? nx * (dy + ny * dz) : (I)0);\n"
-      << "}\n"
-      // the values a lane's vector load cannot give, into f: inside the y-z
-      // footprint only x leaves the row, by less than one row length, so it
-      // wraps (or the value is zero); elsewhere the boundary rule per point
-      << "template <typename T, typename I> __device__ __forceinline__ void dcp_fixld(const T *__restrict__ a, "
-         "T *f, bool inner, I i, I x, I dx, I dy, I dz, I y, I z, I nx, I ny, I nz, int bc) {\n"
-      << "    if (inner) {\n"
-      << "        if (x + dx < 0 || x + dx + V > nx) {\n"
-      << "            const I row = i - x + nx * (dy + ny * dz);\n"
-      << "#pragma unroll\n"
-      << "            for (int j = 0; j < V; ++j) {\n"
-      << "                const I xj = x + j + dx;\n"
-      << "                const I xw = xj < 0 ? xj + nx : (xj >= nx ? xj - nx : xj);\n"
-      << "                if (bc != 0 || xw == xj) f[j] = a[row + xw];\n"
-      << "            }\n"
-      << "        }\n"
-      << "    } else {\n"
-      << "#pragma unroll\n"
-      << "        for (int j = 0; j < V; ++j) f[j] = dcp_ld<T, I>(a, x + j + dx, y + dy, z + dz, nx, ny, nz, bc);\n"
-      << "    }\n"
-      << "}\n"
-      // a lane takes its vector load where it covers the lane's V points
-      << "template <typename T, typename I> __device__ __forceinline__ void dcp_pick(const T *q, const T *f, T *o, "
-         "bool inner, I x, I dx, I nx) {\n"
-      << "    const unsigned long long m = __builtin_amdgcn_ballot_w64(inner && x + dx >= 0 && x + dx + V <= nx);\n"
-      << "#pragma unroll\n"
-      << "    for (int j = 0; j < V; ++j) o[j] = dcp_sel(m, q[j], f[j]);\n"
-      << "}\n"
       << "template <typename T, typename I> __device__ __forceinline__ void dcp_wr(T *__restrict__ a, "
          "const T *o, I i, I x, I nx) {\n"
       << "    if (x + V <= nx) { dcp_stv<T>(a + i, o); return; }\n"
       << "#pragma unroll\n"
       << "    for (int j = 0; j < V; ++j)\n"
       << "        if (x + j < nx) a[i + j] = o[j];\n"
+      << "}\n"
+      // one queue slot: the lane's V x-points of row yy, plane zz (wrapped;
+      // the start clamped into the row); returns whether it reads as data
+      << "template <typename T, typename I> __device__ __forceinline__ bool dcp_slot(const T *__restrict__ a, T *q, "
+         "I xc, I yy, I zz, I nx, I ny, I nz, int bc) {\n"
+      << "    dcp_ldv<T>(a + (xc + nx * (dcp_wrap<I>(yy, ny) + ny * dcp_wrap<I>(zz, nz))), q);\n"
+      << "    return bc != 0 || (dcp_in<I>(yy, ny) && dcp_in<I>(zz, nz));\n"
+      << "}\n"
+      // V points (x + j + dx, yy, zz) through the boundary rule, one wrap
+      // per axis at most; f holds zeros on entry
+      << "template <typename T, typename I> __device__ __forceinline__ void dcp_fixel(const T *__restrict__ a, T *f, "
+         "I x, I dx, I yy, I zz, I nx, I ny, I nz, int bc) {\n"
+      << "    const bool inyz = dcp_in<I>(yy, ny) && dcp_in<I>(zz, nz);\n"
+      << "    const I row = nx * (dcp_wrap<I>(yy, ny) + ny * dcp_wrap<I>(zz, nz));\n"
+      << "#pragma unroll\n"
+      << "    for (int j = 0; j < V; ++j) {\n"
+      << "        const I xe = x + j + dx;\n"
+      << "        if (bc != 0 || (inyz && dcp_in<I>(xe, nx))) f[j] = a[row + dcp_wrap<I>(xe, nx)];\n"
+      << "    }\n"
       << "}\n";
     for (size_t k = 0; k < p->kernels.size(); ++k) {
         const Kernel &K = p->kernels[k];
-        // extreme offsets of this kernel's shifted reads
-        int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-        for (int i : K.nodes) {
-            const Node &n = p->nodes[i];
-            if (n.kind != K_SHIFT) continue;
-            const int d[3] = {n.dx, n.dy, n.dz};
-            for (int a = 0; a < 3; ++a) {
-                lo[a] = std::min(lo[a], d[a]);
-                hi[a] = std::max(hi[a], d[a]);
-            }
-        }
         std::ostringstream params_decl, params_pass;
         bool first = true;
         auto sep = [&]() {
@@ -441,67 +435,59 @@ void generate(dcp_fused *p) {
         sep();
         params_decl << "i64 nx_, i64 ny_, i64 nz_, int bc";
         params_pass << "nx_, ny_, nz_, bc";
-        // the kernel's memory reads, in program order (reads have no side
-        // effects, so they all go first)
+
+        // the kernel's memory reads (program order) and their groups
         struct Rd {
-            std::string dst, src;
-            int dx, dy, dz;
+            std::string dst;
+            int field, dx, dy, dz, grp;
+        };
+        struct Grp {
+            int field, dy, dzlo, dzhi;
         };
         std::vector<Rd> rds;
+        std::vector<Grp> grps;
         std::vector<char> loaded(p->nodes.size(), 0);
+        auto add_read = [&](const std::string &dst, int field, int dx, int dy, int dz) {
+            int g = -1;
+            for (size_t q = 0; q < grps.size(); ++q)
+                if (grps[q].field == field && grps[q].dy == dy) g = (int)q;
+            if (g < 0) {
+                grps.push_back(Grp{field, dy, dz, dz});
+                g = (int)grps.size() - 1;
+            }
+            grps[g].dzlo = std::min(grps[g].dzlo, dz);
+            grps[g].dzhi = std::max(grps[g].dzhi, dz);
+            rds.push_back(Rd{dst, field, dx, dy, dz, g});
+        };
         for (int i : K.nodes) {
             const Node &n = p->nodes[i];
             if (n.kind == K_SHIFT) {
-                rds.push_back(Rd{"v" + std::to_string(i), "m" + std::to_string(n.a), n.dx, n.dy, n.dz});
+                add_read("v" + std::to_string(i), n.a, n.dx, n.dy, n.dz);
                 continue;
             }
             for (int o : {n.a, n.b}) {
                 if (o < 0) continue;
                 const Node &m = p->nodes[o];
                 if (!m.field || loaded[o] || !(m.kind == K_INPUT || m.kernel != (int)k)) continue;
-                rds.push_back(Rd{"r" + std::to_string(o), "m" + std::to_string(o), 0, 0, 0});
+                add_read("r" + std::to_string(o), o, 0, 0, 0);
                 loaded[o] = 1;
             }
         }
-        auto offs = [](const Rd &r) {
-            return "(I)(" + std::to_string(r.dx) + "), (I)(" + std::to_string(r.dy) + "), (I)(" +
-                   std::to_string(r.dz) + ")";
-        };
-        std::ostringstream qdecl, fdecl, qpass_a, qpass_b, fpass;
-        for (size_t j = 0; j < rds.size(); ++j) {
-            qdecl << ", " << T << " *q" << j;
-            fdecl << ", " << T << " *f" << j;
-            qpass_a << ", qa" << j;
-            qpass_b << ", qb" << j;
-            fpass << ", fx" << j;
+        int maxd[3] = {0, 0, 0};
+        for (const Rd &r : rds) {
+            maxd[0] = std::max(maxd[0], std::abs(r.dx));
+            maxd[1] = std::max(maxd[1], std::abs(r.dy));
+            maxd[2] = std::max(maxd[2], std::abs(r.dz));
         }
-        // one plane's vector loads; outside the y-z footprint they read the
-        // lane's own row instead (the values are not used), so the loads are
-        // issued on every path
-        s << "template <typename I> __device__ __forceinline__ void " << K.fname << "_issue("
-          << params_decl.str() << ", bool inner, I i, I x, I nx, I ny" << qdecl.str() << ") {\n";
-        for (size_t j = 0; j < rds.size(); ++j)
-            s << "    dcp_ldv<" << T << ">(" << rds[j].src << " + dcp_vidx<I>(inner, i, x, " << offs(rds[j])
-              << ", nx, ny), q" << j << ");\n";
-        s << "}\n";
-        // one plane's row-end and boundary reads
-        s << "template <typename I> __device__ __forceinline__ void " << K.fname << "_fix(" << params_decl.str()
-          << ", bool inner, I x, I y, I z, I i, I nx, I ny, I nz" << fdecl.str() << ") {\n";
-        for (size_t j = 0; j < rds.size(); ++j)
-            s << "#pragma unroll\n"
-              << "    for (int j = 0; j < V; ++j) f" << j << "[j] = " << T << "(0);\n"
-              << "    dcp_fixld<" << T << ", I>(" << rds[j].src << ", f" << j << ", inner, i, x, " << offs(rds[j])
-              << ", y, z, nx, ny, nz, bc);\n";
-        s << "}\n";
-        // the rest of one plane: the choice per lane, the statements and the
-        // stores
-        s << "template <typename I> __device__ __forceinline__ void " << K.fname << "_done(" << params_decl.str()
-          << ", bool inner, I x, I y, I z, I i, I nx, I ny, I nz" << qdecl.str() << fdecl.str() << ") {\n";
-        for (size_t j = 0; j < rds.size(); ++j) s << "    " << T << " " << rds[j].dst << "[V];\n";
-        for (size_t j = 0; j < rds.size(); ++j)
-            s << "    dcp_pick<" << T << ", I>(q" << j << ", f" << j << ", " << rds[j].dst << ", inner, x, (I)("
-              << rds[j].dx << "), nx);\n";
-        // operand o for point j
+
+        // the statements and stores of one plane, given every read's values
+        std::ostringstream rd_decl, rd_pass;
+        for (const Rd &r : rds) {
+            rd_decl << ", const " << T << " *" << r.dst;
+            rd_pass << ", " << r.dst;
+        }
+        s << "template <typename I> __device__ __forceinline__ void " << K.fname << "_comp(" << params_decl.str()
+          << ", I i, I x, I nx" << rd_decl.str() << ") {\n";
         auto val = [&](int o) -> std::string {
             const Node &m = p->nodes[o];
             if (!m.field) return scalar_expr(p, o, T);
@@ -529,87 +515,137 @@ void generate(dcp_fused *p) {
             if (n.stored) s << "    dcp_wr<" << T << ", I>(w" << i << ", v" << i << ", i, x, nx);\n";
         }
         s << "}\n";
+
+        // one plane, every point through the boundary rule (small grids)
+        s << "template <typename I> __device__ __forceinline__ void " << K.fname << "_slow(" << params_decl.str()
+          << ", I x, I y, I z, I i, I nx, I ny, I nz) {\n";
+        for (const Rd &r : rds)
+            s << "    " << T << " " << r.dst << "[V];\n"
+              << "#pragma unroll\n"
+              << "    for (int j = 0; j < V; ++j) " << r.dst << "[j] = dcp_ld<" << T << ", I>(m" << r.field
+              << ", x + j + (" << r.dx << "), y + (" << r.dy << "), z + (" << r.dz << "), nx, ny, nz, bc);\n";
+        s << "    " << K.fname << "_comp<I>(" << params_pass.str() << ", i, x, nx" << rd_pass.str() << ");\n"
+          << "}\n";
+
         for (const char *suffix : {"_i32", "_i64"}) {
             const char *I = suffix[2] == '3' ? "int" : "i64";
-            auto issue = [&](const std::string &inn, const std::string &idx, const std::ostringstream &qp) {
-                return K.fname + "_issue<I>(" + params_pass.str() + ", " + inn + ", " + idx + ", x, nx, ny" +
-                       qp.str() + ")";
-            };
-            auto fix = [&](const std::string &inn, const std::string &z, const std::string &idx) {
-                return K.fname + "_fix<I>(" + params_pass.str() + ", " + inn + ", x, y, " + z + ", " + idx +
-                       ", nx, ny, nz" + fpass.str() + ")";
-            };
-            auto done = [&](const std::string &inn, const std::string &z, const std::string &idx,
-                            const std::ostringstream &qp) {
-                return K.fname + "_done<I>(" + params_pass.str() + ", " + inn + ", x, y, " + z + ", " + idx +
-                       ", nx, ny, nz" + qp.str() + fpass.str() + ")";
-            };
-            std::ostringstream qsets;
-            for (size_t j = 0; j < rds.size(); ++j)
-                qsets << "        " << T << " qa" << j << "[V], qb" << j << "[V], fx" << j << "[V];\n"
-                      << "#pragma unroll\n"
-                      << "        for (int j = 0; j < V; ++j) { qa" << j << "[j] = " << T << "(0); qb" << j
-                      << "[j] = " << T << "(0); }\n";
-            const std::string zin = "iny && (zz) + (" + std::to_string(lo[2]) + ") >= 0 && (zz) + (" +
-                                    std::to_string(hi[2]) + ") < nz";
-            auto zin_at = [&](const std::string &zz) {
-                std::string r = zin;
-                for (size_t pos; (pos = r.find("zz")) != std::string::npos;) r.replace(pos, 2, zz);
-                return r;
-            };
+            std::ostringstream b;  // the fast path's per-tile code
+            // queue slots: Q<g>_<k> holds plane z + dzlo + k; P<g> the next top
+            for (size_t g = 0; g < grps.size(); ++g) {
+                const int span = grps[g].dzhi - grps[g].dzlo + 1;
+                for (int q = 0; q < span; ++q)
+                    b << "        " << T << " Q" << g << "_" << q << "[V];\n"
+                      << "        bool W" << g << "_" << q << " = dcp_slot<" << T << ", I>(m" << grps[g].field << ", Q"
+                      << g << "_" << q << ", xc, y + (" << grps[g].dy << "), zb + (" << grps[g].dzlo + q
+                      << "), nx, ny, nz, bc);\n";
+                b << "        " << T << " P" << g << "[V];\n";
+            }
+            b << "        for (I z = zb; z < ze; ++z, i += plane) {\n";
+            // the lanes that take a read's values per point, and those values
+            for (size_t r = 0; r < rds.size(); ++r) {
+                const Rd &R = rds[r];
+                std::string nf;
+                if (std::abs(R.dx) > V)
+                    nf = "true";
+                else if (R.dx == 0)
+                    nf = "x + V > nx";
+                else if (R.dx < 0)
+                    nf = "x + V > nx || lane == 0";
+                else
+                    nf = "lane == 63 || x + 2 * V > nx";
+                b << "            const bool nf" << r << " = " << nf << ";\n"
+                  << "            " << T << " f" << r << "[V];\n"
+                  << "#pragma unroll\n"
+                  << "            for (int j = 0; j < V; ++j) f" << r << "[j] = " << T << "(0);\n"
+                  << "            if (nf" << r << ") dcp_fixel<" << T << ", I>(m" << R.field << ", f" << r << ", x, (I)("
+                  << R.dx << "), y + (" << R.dy << "), z + (" << R.dz << "), nx, ny, nz, bc);\n";
+            }
+            // the next plane's top slot of every group, on every path (loads
+            // complete in order: the per-point loads above go out first, so
+            // waiting for them does not wait for these)
+            for (size_t g = 0; g < grps.size(); ++g)
+                b << "            const bool WP" << g << " = dcp_slot<" << T << ", I>(m" << grps[g].field << ", P" << g
+                  << ", xc, y + (" << grps[g].dy << "), z + (" << grps[g].dzhi + 1 << "), nx, ny, nz, bc);\n";
+            // each read from its slot: element j is element j + dx of this
+            // lane's vector, or of the lower / upper lane's
+            for (size_t r = 0; r < rds.size(); ++r) {
+                const Rd &R = rds[r];
+                const std::string slot =
+                    "Q" + std::to_string(R.grp) + "_" + std::to_string(R.dz - grps[R.grp].dzlo);
+                const std::string valid =
+                    "W" + std::to_string(R.grp) + "_" + std::to_string(R.dz - grps[R.grp].dzlo);
+                b << "            " << T << " " << R.dst << "[V];\n";
+                if (std::abs(R.dx) > V) {
+                    b << "#pragma unroll\n"
+                      << "            for (int j = 0; j < V; ++j) " << R.dst << "[j] = f" << r << "[j];\n";
+                    continue;
+                }
+                b << "            {\n"
+                  << "                " << T << " c[V];\n";
+                for (int j = 0; j < V; ++j) {
+                    const int e = j + R.dx;
+                    std::string src;
+                    if (e < 0)
+                        src = "dcp_dpp<DCP_LOWER>(" + slot + "[" + std::to_string(e + V) + "])";
+                    else if (e >= V)
+                        src = "dcp_dpp<DCP_UPPER>(" + slot + "[" + std::to_string(e - V) + "])";
+                    else
+                        src = slot + "[" + std::to_string(e) + "]";
+                    b << "                c[" << j << "] = " << valid << " ? " << src << " : " << T << "(0);\n";
+                }
+                b << "                const unsigned long long mk = __builtin_amdgcn_ballot_w64(nf" << r << ");\n"
+                  << "#pragma unroll\n"
+                  << "                for (int j = 0; j < V; ++j) " << R.dst << "[j] = dcp_sel(mk, f" << r
+                  << "[j], c[j]);\n"
+                  << "            }\n";
+            }
+            b << "            " << K.fname << "_comp<I>(" << params_pass.str() << ", i, x, nx" << rd_pass.str()
+              << ");\n";
+            // the queues move up one plane
+            for (size_t g = 0; g < grps.size(); ++g) {
+                const int span = grps[g].dzhi - grps[g].dzlo + 1;
+                for (int q = 0; q + 1 < span; ++q)
+                    b << "#pragma unroll\n"
+                      << "            for (int j = 0; j < V; ++j) Q" << g << "_" << q << "[j] = Q" << g << "_" << q + 1
+                      << "[j];\n"
+                      << "            W" << g << "_" << q << " = W" << g << "_" << q + 1 << ";\n";
+                b << "#pragma unroll\n"
+                  << "            for (int j = 0; j < V; ++j) Q" << g << "_" << span - 1 << "[j] = P" << g << "[j];\n"
+                  << "            W" << g << "_" << span - 1 << " = WP" << g << ";\n";
+            }
+            b << "        }\n";
+
             s << "extern \"C\" __global__ void __launch_bounds__(256) " << K.fname << suffix << "("
               << params_decl.str() << ", int zr, i64 tiles_x_, i64 nchunk_) {\n"
               << "    typedef " << I << " I;\n"
               << "    const I nx = (I)nx_, ny = (I)ny_, nz = (I)nz_, tiles_x = (I)tiles_x_;\n"
               << "    const I nb = tiles_x * ny * (I)nchunk_, nwg = (nb + 3) / 4;\n"
-              << "    const I G = (I)gridDim.x, b = (I)blockIdx.x;\n"
+              << "    const I G = (I)gridDim.x, bk = (I)blockIdx.x;\n"
               // workgroups go to the 8 XCDs in turn: give each XCD one
               // contiguous range of tiles so row neighbours share its L2
-              << "    const I xcd = b % 8, k = b / 8, q = G / 8, r = G % 8;\n"
-              << "    const I lb = xcd < r ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;\n"
+              << "    const I xcd = bk % 8, kq = bk / 8, q = G / 8, r = G % 8;\n"
+              << "    const I lb = xcd < r ? xcd * (q + 1) + kq : r * (q + 1) + (xcd - r) * q + kq;\n"
               << "    const I wv = (I)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));\n"
               << "    const I lane = (I)(threadIdx.x & 63);\n"
               << "    const I plane = nx * ny;\n"
+              // one wrap per axis reaches every neighbour
+              << "    const bool fast = nx >= V + " << maxd[0] << " && ny >= " << maxd[1] << " && nz > " << maxd[2]
+              << ";\n"
               << "    for (I L = lb; L < nwg; L += G) {\n"
               << "        const I wt = L * 4 + wv;\n"
               << "        if (wt >= nb) continue;\n"
               << "        const I xt = wt % tiles_x, t = wt / tiles_x, y = t % ny, zb = (t / ny) * (I)zr;\n"
               << "        const I x = xt * " << 64 * V << " + lane * V;\n"
               << "        if (x >= nx) continue;\n"
-              << "        const bool iny = y + (" << lo[1] << ") >= 0 && y + (" << hi[1] << ") < ny;\n"
               << "        const I ze = (zb + (I)zr < nz ? zb + (I)zr : nz);\n"
               << "        I i = x + nx * y + plane * zb;\n"
-              // two register sets: the next plane's vector loads are in
-              // flight while this plane is finished
-              << qsets.str()
-              // rows shorter than V points plus the largest x offset: every
-              // point through the boundary rule
-              << "        if (nx < V + " << std::max(-lo[0], hi[0]) << ") {\n"
-              << "            for (I z = zb; z < ze; ++z, i += plane) {\n"
-              << "                " << fix("false", "z", "i") << ";\n"
-              << "                " << done("false", "z", "i", qpass_a) << ";\n"
-              << "            }\n"
+              << "        if (!fast) {\n"
+              << "            for (I z = zb; z < ze; ++z, i += plane)\n"
+              << "                " << K.fname << "_slow<I>(" << params_pass.str() << ", x, y, z, i, nx, ny, nz);\n"
               << "            continue;\n"
               << "        }\n"
-              // loads complete in order: a plane's row-end reads go out
-              // before the next plane's vector loads, so waiting for the
-              // former does not wait for the latter; the next plane's loads
-              // go out on every path (past the chunk's end they re-read
-              // this row, unused)
-              << "        bool ia = " << zin_at("zb") << ", ib = false;\n"
-              << "        " << issue("ia", "i", qpass_a) << ";\n"
-              << "        for (I z = zb; z < ze; z += 2, i += 2 * plane) {\n"
-              << "            " << fix("ia", "z", "i") << ";\n"
-              << "            ib = z + 1 < ze && " << zin_at("z + 1") << ";\n"
-              << "            " << issue("ib", "(z + 1 < ze ? i + plane : i)", qpass_b) << ";\n"
-              << "            " << done("ia", "z", "i", qpass_a) << ";\n"
-              << "            if (z + 1 >= ze) break;\n"
-              << "            " << fix("ib", "z + 1", "i + plane") << ";\n"
-              << "            ia = z + 2 < ze && " << zin_at("z + 2") << ";\n"
-              << "            " << issue("ia", "(z + 2 < ze ? i + 2 * plane : i)", qpass_a) << ";\n"
-              << "            " << done("ib", "z + 1", "i + plane", qpass_b) << ";\n"
-              << "        }\n"
-              << "    }\n"
+              << "        const I xc = x + V <= nx ? x : nx - V;\n"
+              << b.str() << "    }\n"
               << "}\n";
         }
     }
