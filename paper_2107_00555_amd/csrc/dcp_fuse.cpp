@@ -273,7 +273,9 @@ void plan(dcp_fused *p) {
             }
             if (n.stored) K.writes.push_back(i);
         }
-        K.fname = "dcp_fused_k" + std::to_string(k);
+        // named by dtype and mode, so profiles tell the programs apart
+        K.fname = std::string("dcp_gen_") + (p->dtype == DCP_F64 ? "f64" : "f32") + (p->fuse ? "_fused" : "_unfused") +
+                  "_k" + std::to_string(k);
     }
 }
 
@@ -540,25 +542,49 @@ void generate(dcp_fused *p) {
                       << "), nx, ny, nz, bc);\n";
                 b << "        " << T << " P" << g << "[V];\n";
             }
-            b << "        for (I z = zb; z < ze; ++z, i += plane) {\n";
-            // the lanes that take a read's values per point, and those values
+            b << "        for (I z = zb; z < ze; ++z, i += plane) {\n"
+              // a lane past a ragged row end (V points not all in the row)
+              << "            const bool rg = x + V > nx;\n"
+              << "            const unsigned long long mrg = __builtin_amdgcn_ballot_w64(rg);\n";
+            // per read: the elements from outside the lane at a wave or row
+            // end (one load each, into scalars of their own), and, in a wave
+            // with a ragged lane, that lane's points through the rule
             for (size_t r = 0; r < rds.size(); ++r) {
                 const Rd &R = rds[r];
-                std::string nf;
-                if (std::abs(R.dx) > V)
-                    nf = "true";
-                else if (R.dx == 0)
-                    nf = "x + V > nx";
-                else if (R.dx < 0)
-                    nf = "x + V > nx || lane == 0";
-                else
-                    nf = "lane == 63 || x + 2 * V > nx";
-                b << "            const bool nf" << r << " = " << nf << ";\n"
-                  << "            " << T << " f" << r << "[V];\n"
+                const std::string yz = "y + (" + std::to_string(R.dy) + "), z + (" + std::to_string(R.dz) + ")";
+                if (std::abs(R.dx) > V) {
+                    b << "            " << T << " f" << r << "[V];\n"
+                      << "#pragma unroll\n"
+                      << "            for (int j = 0; j < V; ++j) f" << r << "[j] = " << T << "(0);\n"
+                      << "            dcp_fixel<" << T << ", I>(m" << R.field << ", f" << r << ", x, (I)(" << R.dx
+                      << "), " << yz << ", nx, ny, nz, bc);\n";
+                    continue;
+                }
+                if (R.dx != 0) {
+                    const std::string ne = R.dx < 0 ? "lane == 0" : "lane == 63 || x + 2 * V > nx";
+                    b << "            const bool ne" << r << " = " << ne << ";\n";
+                    for (int j = 0; j < V; ++j) {
+                        const int e = j + R.dx;
+                        if (e >= 0 && e < V) continue;
+                        b << "            " << T << " e" << r << "_" << j << " = " << T << "(0);\n";
+                    }
+                    b << "            if (ne" << r << ") {\n"
+                      << "                const I yy = y + (" << R.dy << "), zz = z + (" << R.dz << ");\n"
+                      << "                const bool inyz = dcp_in<I>(yy, ny) && dcp_in<I>(zz, nz);\n"
+                      << "                const I row = nx * (dcp_wrap<I>(yy, ny) + ny * dcp_wrap<I>(zz, nz));\n";
+                    for (int j = 0; j < V; ++j) {
+                        const int e = j + R.dx;
+                        if (e >= 0 && e < V) continue;
+                        b << "                { const I xe = x + " << e << "; if (bc != 0 || (inyz && dcp_in<I>(xe, nx))) e"
+                          << r << "_" << j << " = m" << R.field << "[row + dcp_wrap<I>(xe, nx)]; }\n";
+                    }
+                    b << "            }\n";
+                }
+                b << "            " << T << " g" << r << "[V];\n"
                   << "#pragma unroll\n"
-                  << "            for (int j = 0; j < V; ++j) f" << r << "[j] = " << T << "(0);\n"
-                  << "            if (nf" << r << ") dcp_fixel<" << T << ", I>(m" << R.field << ", f" << r << ", x, (I)("
-                  << R.dx << "), y + (" << R.dy << "), z + (" << R.dz << "), nx, ny, nz, bc);\n";
+                  << "            for (int j = 0; j < V; ++j) g" << r << "[j] = " << T << "(0);\n"
+                  << "            if (mrg != 0 && rg) dcp_fixel<" << T << ", I>(m" << R.field << ", g" << r << ", x, (I)("
+                  << R.dx << "), " << yz << ", nx, ny, nz, bc);\n";
             }
             // the next plane's top slot of every group, on every path (loads
             // complete in order: the per-point loads above go out first, so
@@ -580,8 +606,9 @@ void generate(dcp_fused *p) {
                       << "            for (int j = 0; j < V; ++j) " << R.dst << "[j] = f" << r << "[j];\n";
                     continue;
                 }
-                b << "            {\n"
-                  << "                " << T << " c[V];\n";
+                b << "            {\n";
+                if (R.dx != 0)
+                    b << "                const unsigned long long mne = __builtin_amdgcn_ballot_w64(ne" << r << ");\n";
                 for (int j = 0; j < V; ++j) {
                     const int e = j + R.dx;
                     std::string src;
@@ -591,13 +618,13 @@ void generate(dcp_fused *p) {
                         src = "dcp_dpp<DCP_UPPER>(" + slot + "[" + std::to_string(e - V) + "])";
                     else
                         src = slot + "[" + std::to_string(e) + "]";
-                    b << "                c[" << j << "] = " << valid << " ? " << src << " : " << T << "(0);\n";
+                    std::string c = "(" + valid + " ? " + src + " : " + T + "(0))";
+                    if (e < 0 || e >= V)
+                        c = "dcp_sel(mne, e" + std::to_string(r) + "_" + std::to_string(j) + ", " + c + ")";
+                    b << "                " << R.dst << "[" << j << "] = dcp_sel(mrg, g" << r << "[" << j << "], " << c
+                      << ");\n";
                 }
-                b << "                const unsigned long long mk = __builtin_amdgcn_ballot_w64(nf" << r << ");\n"
-                  << "#pragma unroll\n"
-                  << "                for (int j = 0; j < V; ++j) " << R.dst << "[j] = dcp_sel(mk, f" << r
-                  << "[j], c[j]);\n"
-                  << "            }\n";
+                b << "            }\n";
             }
             b << "            " << K.fname << "_comp<I>(" << params_pass.str() << ", i, x, nx" << rd_pass.str()
               << ");\n";
@@ -810,6 +837,10 @@ int dcp_fuse_run(dcp_fused *p, const void *const *inputs, const double *params, 
     int64_t tiles_x = (nx + tile_w - 1) / tile_w;
     int64_t zr = 1;
     while (zr < 16 && tiles_x * ny * ((nz + 2 * zr - 1) / (2 * zr)) >= 4 * 4096) zr *= 2;
+    if (const char *e = std::getenv("DCP_FUSE_ZR")) {  // tuning override: planes per wave tile
+        const long v = std::strtol(e, nullptr, 10);
+        if (v >= 1 && v <= 4096) zr = v;
+    }
     int64_t nchunk = (nz + zr - 1) / zr;
     const unsigned grid = (unsigned)std::min<int64_t>((tiles_x * ny * nchunk + 3) / 4, 1 << 20);
     int zr32 = (int)zr;

@@ -50,7 +50,7 @@ def test_shift_of_a_temporary_starts_a_kernel(F):
     fz = P.compile()
     assert fz.n_kernels == 2 and fz.n_buffers == 2
     src = fz.source
-    assert "dcp_fused_k0" in src and "dcp_fused_k1" in src and "float" in src
+    assert "dcp_gen_f32_fused_k0" in src and "dcp_gen_f32_fused_k1" in src and "float" in src
 
 
 def test_chain_of_shifted_temporaries(F):
