@@ -363,7 +363,10 @@ int dcp_revolve_schedule(int64_t T, int32_t nslots, int64_t *ops, int64_t cap,
  * dcp_fuse_run: inputs[] and outputs[] in declaration order (device
  *   pointers; outputs must not overlap inputs, each other or ws), params[]
  *   (host doubles).  Loads the code on the current device at its first run
- *   there.  A program object is used by one thread at a time.
+ *   there (under a lock: several threads may run one program object, each
+ *   on its own outputs and workspace).  Runs are asynchronous on the given
+ *   stream; dcp_fuse_free first waits for every device the program was
+ *   loaded on.
  */
 typedef struct dcp_fused dcp_fused;
 

@@ -40,6 +40,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -96,8 +97,17 @@ struct dcp_fused {
     std::string source;
     std::vector<char> code;                    // compiled code object
     std::map<int, std::pair<hipModule_t, std::vector<hipFunction_t>>> modules;  // per device
+    std::mutex modules_mu;                     // guards modules (runs from several threads)
     ~dcp_fused() {
-        for (auto &m : modules) hipModuleUnload(m.second.first);
+        // runs may still be in flight: wait for each device that holds the
+        // code before unloading it
+        int cur = 0;
+        const bool have_cur = hipGetDevice(&cur) == hipSuccess;
+        for (auto &m : modules) {
+            if (hipSetDevice(m.first) == hipSuccess) (void)hipDeviceSynchronize();
+            hipModuleUnload(m.second.first);
+        }
+        if (have_cur && !modules.empty()) (void)hipSetDevice(cur);
     }
 };
 
@@ -805,6 +815,7 @@ int dcp_fuse_run(dcp_fused *p, const void *const *inputs, const double *params, 
 
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return DCP_E_HIP;
+    std::unique_lock<std::mutex> lock(p->modules_mu);
     auto it = p->modules.find(dev);
     if (it == p->modules.end()) {
         hipModule_t m;
@@ -822,6 +833,8 @@ int dcp_fuse_run(dcp_fused *p, const void *const *inputs, const double *params, 
         }
         it = p->modules.emplace(dev, std::make_pair(m, fns)).first;
     }
+    const std::vector<hipFunction_t> &fns = it->second.second;  // stable once inserted
+    lock.unlock();
     auto ptr_of = [&](int node) -> void * {
         const Node &m = p->nodes[node];
         if (m.kind == K_INPUT) return const_cast<void *>(inputs[m.slot]);
@@ -874,7 +887,7 @@ int dcp_fuse_run(dcp_fused *p, const void *const *inputs, const double *params, 
         args.push_back(&zr32);
         args.push_back(&tiles_x);
         args.push_back(&nchunk);
-        hipFunction_t fn = it->second.second[2 * k + (idx32 ? 0 : 1)];
+        hipFunction_t fn = fns[2 * k + (idx32 ? 0 : 1)];
         if (hipModuleLaunchKernel(fn, grid, 1, 1, 256, 1, 1, 0, st, args.data(),
                                   nullptr) != hipSuccess)
             return DCP_E_HIP;

@@ -142,3 +142,52 @@ def test_run_argument_errors():
         prog.run([u, u.clone()], PARAMS, outputs=[u])   # output aliases an input
     with pytest.raises(_lib.DcpError):
         prog.run([u, u.clone()], dict(PARAMS, alpha=float("nan")))
+
+
+def test_two_threads_share_one_program():
+    # the first run on the device loads the code under a lock; both threads'
+    # results equal the interpreter's
+    import threading
+    P = step_program("f64")
+    prog = P.compile()
+    shape = (40, 12, 9)
+    u0, f = rand_fields(shape, 1200)
+    (want,) = fuse_interp.run(P.text(), [u0, f], PARAMS, 1)
+    u, fd = to_dev(u0), to_dev(f)
+    outs = [torch.empty_like(u) for _ in range(2)]
+    errs = []
+
+    def work(o):
+        try:
+            for _ in range(5):
+                prog.run([u, fd], PARAMS, bc=1, outputs=[o])
+            torch.cuda.synchronize()
+        except Exception as e:          # reported below
+            errs.append(e)
+
+    say("fuse two threads")
+    ts = [threading.Thread(target=work, args=(o,)) for o in outs]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    assert not errs, errs
+    for o in outs:
+        assert np.array_equal(to_host(o), want)
+
+
+def test_free_right_after_a_run():
+    # freeing the program waits for the device before unloading the code
+    P = step_program("f32")
+    shape = (300, 20, 16)
+    u0, f = rand_fields(shape, 1201)
+    u0, f = u0.astype(np.float32), f.astype(np.float32)
+    (want,) = fuse_interp.run(P.text(), [u0, f], PARAMS, 0)
+    u, fd = to_dev(u0, torch.float32), to_dev(f, torch.float32)
+    out = torch.empty_like(u)
+    say("fuse free after run")
+    prog = P.compile()
+    prog.run([u, fd], PARAMS, bc=0, outputs=[out])
+    del prog
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(out), want)
