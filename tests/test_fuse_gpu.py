@@ -191,3 +191,42 @@ def test_free_right_after_a_run():
     del prog
     torch.cuda.synchronize()
     assert np.array_equal(to_host(out), want)
+
+
+def shifts_program(dtype):
+    # shifts beyond the lane width (|dx| > V), exactly +-V, a z-queue of five
+    # planes, several rows of one field, and a chained shift of a temporary
+    F = _fuse()
+    P = F.Program(dtype)
+    a, b = P.input("a", "b")
+    (p,) = P.param("p")
+    s = (a.shift(5, 0, 0) + a.shift(-7, 2, -1)) + (a.shift(0, -3, 3) + a.shift(9, 0, 0))
+    s = s + (a.shift(2, 0, 0) - a.shift(-2, 0, 0)) + (a.shift(4, 1, 0) - a.shift(-4, -1, 0))
+    q = (b.shift(0, 0, -2) + b.shift(0, 0, -1)) + (b.shift(0, 0, 1) + b.shift(0, 0, 2)) + p * b
+    P.output("o", s * 0.25 + q)
+    P.output("r", (s - q).shift(1, -1, 1))
+    return P
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("bc", [0, 1])
+@pytest.mark.parametrize("shape", [
+    (300, 7, 6),     # (nx, ny, nz): every fast-path condition holds (nx >= V + 9, ny >= 3, nz > 3)
+    (13, 3, 4),      # the shortest rows on the fast path in float32 (nx = V + 9 with V = 4)
+    (12, 3, 4),      # one point shorter: per-point path in float32, fast path in float64 (V = 2)
+    (64, 2, 3),      # ny < 3, nz = 3: every point through the rule
+    (517, 5, 9),     # ragged row end in both dtypes
+])
+def test_large_and_long_shifts_bitwise(shape, bc, dtype):
+    P = shifts_program(dtype)
+    dt = np.float64 if dtype == "f64" else np.float32
+    r = np.random.default_rng(sum(shape) + bc)
+    nx, ny, nz = shape
+    arrays = [r.uniform(-1, 1, (nz, ny, nx)).astype(dt) for _ in range(2)]
+    want = fuse_interp.run(P.text(), arrays, {"p": 0.375}, bc)
+    for fuse in (True, False):
+        prog = P.compile(fuse)
+        say("fuse shifts", shape, bc, dtype, fuse, prog.n_kernels)
+        got = run_gpu(prog, arrays, {"p": 0.375}, bc)
+        for g, w in zip(got, want):
+            assert np.array_equal(g, w), (shape, bc, dtype, fuse)
