@@ -126,10 +126,10 @@ def counter_traffic(tblock):
 
 
 def cpu_baseline(u0, f, coeffs, bc):
-    """The oracle as it stands, serial, on 2 of the 100 steps of the same
-    512^3 workload (full grid)."""
+    """The oracle as it stands, serial, on 15 of the 100 steps of the same
+    512^3 workload (full grid; about 20 s on one host core)."""
     import oracle
-    T = 5
+    T = 15
     t0 = time.perf_counter()
     oracle.run(u0, f, coeffs, T, bc, norms=True)
     dt = time.perf_counter() - t0
