@@ -100,3 +100,97 @@ def run(text: str, inputs, params=None, bc: int = 0) -> list:
                     raise ValueError(f"unknown op {op}")
             env[name] = r.astype(dt) if isinstance(r, np.ndarray) else dt(r)
     return [np.asarray(env[n], dtype=dt) for n in outs]
+
+
+def run_points(text: str, inputs, params=None, bc: int = 0, points=()) -> "np.ndarray":
+    """The outputs at the given points only, each point (z, y, x).
+
+    Every statement is evaluated per point, as in run(): an operation rounds
+    once in the program's dtype, and a shift evaluates its operand at the
+    shifted point under the boundary rule (zero outside the grid, or indices
+    mod n).  Inputs may be any objects indexed as a[z, y, x] whose elements
+    convert with float() (so very large fields need not be copied whole).
+    Returns an array [outputs, points] of the program's dtype."""
+    dt = None
+    in_names, par_names, outs = [], [], []
+    defs = {}
+    for raw in text.splitlines():
+        t = raw.split("#", 1)[0].split()
+        if not t:
+            continue
+        if t[0] == "dtype":
+            dt = {"f64": np.float64, "f32": np.float32}[t[1]]
+        elif t[0] == "input":
+            in_names += t[1:]
+        elif t[0] == "param":
+            par_names += t[1:]
+        elif t[0] == "output":
+            outs += t[1:]
+        else:
+            assert t[1] == "=", raw
+            defs[t[0]] = (t[2], t[3:])
+    if dt is None:
+        raise ValueError("missing dtype")
+    inputs = list(inputs)
+    if len(inputs) != len(in_names):
+        raise ValueError("input count")
+    arrs = dict(zip(in_names, inputs))
+    if isinstance(params, dict):
+        params = [params[n] for n in par_names]
+    scal = {n: dt(v) for n, v in zip(par_names, list(params or []))}
+    nz, ny, nx = inputs[0].shape
+    memo = {}
+
+    def is_field(name):
+        if name in arrs:
+            return True
+        if name not in defs:
+            return False
+        op, args = defs[name]
+        return op == "shift" or any(is_field(a) for a in (args[:1] if op == "shift" else args))
+
+    def val(name, z, y, x):
+        if name in scal:
+            return scal[name]
+        if name in arrs:
+            return dt(float(arrs[name][z, y, x]))
+        if name not in defs:
+            return dt(float(name))                       # a literal
+        key = (name, z, y, x) if is_field(name) else (name,)
+        if key in memo:
+            return memo[key]
+        op, args = defs[name]
+        with np.errstate(all="ignore"):
+            if op == "shift":
+                zz, yy, xx = z + int(args[3]), y + int(args[2]), x + int(args[1])
+                if bc == 1:
+                    r = val(args[0], zz % nz, yy % ny, xx % nx)
+                elif 0 <= zz < nz and 0 <= yy < ny and 0 <= xx < nx:
+                    r = val(args[0], zz, yy, xx)
+                else:
+                    r = dt(0)
+            elif op == "neg":
+                r = -val(args[0], z, y, x)
+            elif op == "copy":
+                r = val(args[0], z, y, x)
+            else:
+                a, b = val(args[0], z, y, x), val(args[1], z, y, x)
+                if op == "add":
+                    r = a + b
+                elif op == "sub":
+                    r = a - b
+                elif op == "mul":
+                    r = a * b
+                elif op == "div":
+                    r = a / b
+                else:
+                    raise ValueError(f"unknown op {op}")
+        r = dt(r)
+        memo[key] = r
+        return r
+
+    out = np.empty((len(outs), len(points)), dtype=dt)
+    for j, (z, y, x) in enumerate(points):
+        for i, name in enumerate(outs):
+            out[i, j] = val(name, int(z), int(y), int(x))
+    return out

@@ -230,3 +230,33 @@ def test_large_and_long_shifts_bitwise(shape, bc, dtype):
         got = run_gpu(prog, arrays, {"p": 0.375}, bc)
         for g, w in zip(got, want):
             assert np.array_equal(g, w), (shape, bc, dtype, fuse)
+
+
+def test_grid_beyond_32_bit_indices_sampled():
+    # 2048 x 1024 x 1030 float32 points (8.6 GB a field): point indices pass
+    # 2^31, so the 64-bit index variant runs; outputs are checked at the
+    # corners, along the last planes (indices above 2^31) and at random
+    # points against the per-point interpreter (inputs read from the device
+    # one point at a time)
+    P = step_program("f32")
+    prog = P.compile()
+    nx, ny, nz = 2048, 1024, 1030
+    assert nx * ny * nz > 2 ** 31
+    g = torch.Generator(device=DEV).manual_seed(77)
+    u = torch.rand((nz, ny, nx), generator=g, device=DEV, dtype=torch.float32) * 2 - 1
+    f = torch.rand((nz, ny, nx), generator=g, device=DEV, dtype=torch.float32) * 2 - 1
+    r = np.random.default_rng(78)
+    pts = [(z, y, x) for z in (0, nz - 1) for y in (0, ny - 1) for x in (0, 1, nx - 2, nx - 1)]
+    pts += [(nz - 1, int(y), int(x)) for y, x in zip(r.integers(0, ny, 40), r.integers(0, nx, 40))]
+    pts += [(int(z), int(y), int(x)) for z, y, x in zip(r.integers(0, nz, 60), r.integers(0, ny, 60),
+                                                         r.integers(0, nx, 60))]
+    for bc in (0, 1):
+        say("fuse beyond 32-bit indices", (nx, ny, nz), bc)
+        (out,) = prog.run([u, f], PARAMS, bc=bc)
+        torch.cuda.synchronize()
+        want = fuse_interp.run_points(P.text(), [u, f], PARAMS, bc, pts)[0]
+        got = np.array([out[z, y, x].item() for z, y, x in pts], dtype=np.float32)
+        assert np.array_equal(got, want), bc
+        del out
+    del u, f
+    torch.cuda.empty_cache()

@@ -103,3 +103,23 @@ def test_scalar_statements_and_params():
     u = np.full((2, 2, 2), 2.0)
     y, w = fuse_interp.run(text, [u], {"p": 0.5})
     assert np.all(y == 0.75) and np.all(w == -0.75)
+
+
+@pytest.mark.parametrize("seed", [0, 4, 9])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("bc", [0, 1])
+def test_run_points_equals_whole_grid_run(seed, dtype, bc):
+    # the per-point evaluation (used at grid sizes the whole-array run cannot
+    # hold) gives every output at every point exactly as run() does
+    from fuse_programs import random_program
+    P = random_program(seed, dtype)
+    dt = np.float64 if dtype == "f64" else np.float32
+    r = np.random.default_rng(seed + 5)
+    shape = (4, 5, 6)
+    arrays = [r.uniform(-1, 1, shape).astype(dt) for _ in range(3)]
+    params = {"p": float(r.uniform(-1, 1)), "q": float(r.uniform(-1, 1))}
+    want = fuse_interp.run(P.text(), arrays, params, bc)
+    pts = [(z, y, x) for z in range(4) for y in range(5) for x in range(6)]
+    got = fuse_interp.run_points(P.text(), arrays, params, bc, pts)
+    for i, w in enumerate(want):
+        assert got.dtype == w.dtype and np.array_equal(got[i], w.reshape(-1))
