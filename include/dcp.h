@@ -342,7 +342,8 @@ int dcp_revolve_schedule(int64_t T, int32_t nslots, int64_t *ops, int64_t cap,
  *                              run's boundary rule (DCP_DIRICHLET0: 0
  *                              outside; DCP_PERIODIC: indices mod n)
  *     output NAME ...          fields written to memory
- * Operands are names defined above or numeric literals.  Every statement is
+ * Operands are names defined above or numeric literals (finite doubles,
+ * rounded to the dtype once).  Every statement is
  * one map over the grid (a scalar when all its operands are scalars) and
  * rounds once, so the result equals the statement-by-statement evaluation
  * bit for bit, fused or not.

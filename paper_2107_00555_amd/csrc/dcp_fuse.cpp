@@ -128,6 +128,10 @@ struct Parser {
         char *end = nullptr;
         const double v = std::strtod(tok.c_str(), &end);
         if (end && *end == '\0' && !tok.empty() && !is_ident(tok)) {
+            if (!std::isfinite(v)) {
+                fail(line, "literal '" + tok + "' is not a finite double");
+                return -1;
+            }
             Node n;
             n.kind = K_CONST;
             n.cval = v;

@@ -75,6 +75,7 @@ def test_chain_of_shifted_temporaries(F):
     ("dtype f16\ninput u\n", "dtype"),
     ("dtype f64\ninput u\ny = shift u 1 x 0\noutput y\n", "bad shift"),
     ("dtype f64\ninput 9u\n", "bad name"),
+    ("dtype f64\ninput u\ny = mul u 1e999\noutput y\n", "not a finite"),
 ])
 def test_program_errors(F, text, msg):
     with pytest.raises(F.FuseError, match=msg):
