@@ -607,39 +607,51 @@ void generate(dcp_fused *p) {
                 b << "            const bool WP" << g << " = dcp_slot<" << T << ", I>(m" << grps[g].field << ", P" << g
                   << ", xc, y + (" << grps[g].dy << "), z + (" << grps[g].dzhi + 1 << "), nx, ny, nz, bc);\n";
             // each read from its slot: element j is element j + dx of this
-            // lane's vector, or of the lower / upper lane's
-            for (size_t r = 0; r < rds.size(); ++r) {
-                const Rd &R = rds[r];
-                const std::string slot =
-                    "Q" + std::to_string(R.grp) + "_" + std::to_string(R.dz - grps[R.grp].dzlo);
-                const std::string valid =
-                    "W" + std::to_string(R.grp) + "_" + std::to_string(R.dz - grps[R.grp].dzlo);
-                b << "            " << T << " " << R.dst << "[V];\n";
-                if (std::abs(R.dx) > V) {
-                    b << "#pragma unroll\n"
-                      << "            for (int j = 0; j < V; ++j) " << R.dst << "[j] = f" << r << "[j];\n";
-                    continue;
-                }
-                b << "            {\n";
-                if (R.dx != 0)
-                    b << "                const unsigned long long mne = __builtin_amdgcn_ballot_w64(ne" << r << ");\n";
-                for (int j = 0; j < V; ++j) {
-                    const int e = j + R.dx;
-                    std::string src;
-                    if (e < 0)
-                        src = "dcp_dpp<DCP_LOWER>(" + slot + "[" + std::to_string(e + V) + "])";
-                    else if (e >= V)
-                        src = "dcp_dpp<DCP_UPPER>(" + slot + "[" + std::to_string(e - V) + "])";
-                    else
-                        src = slot + "[" + std::to_string(e) + "]";
-                    std::string c = "(" + valid + " ? " + src + " : " + T + "(0))";
-                    if (e < 0 || e >= V)
-                        c = "dcp_sel(mne, e" + std::to_string(r) + "_" + std::to_string(j) + ", " + c + ")";
-                    b << "                " << R.dst << "[" << j << "] = dcp_sel(mrg, g" << r << "[" << j << "], " << c
-                      << ");\n";
-                }
-                b << "            }\n";
+            // lane's vector, or of the lower / upper lane's.  In a wave with no
+            // ragged lane whose slots all read as data (every periodic plane,
+            // and every interior one) only the row-end elements need a choice.
+            for (size_t r = 0; r < rds.size(); ++r) b << "            " << T << " " << rds[r].dst << "[V];\n";
+            std::string allw = "mrg == 0";
+            for (size_t g = 0; g < grps.size(); ++g) {
+                const int span = grps[g].dzhi - grps[g].dzlo + 1;
+                for (int q = 0; q < span; ++q) allw += " && W" + std::to_string(g) + "_" + std::to_string(q);
             }
+            for (int general = 0; general < 2; ++general) {
+                b << (general ? "            } else {\n" : "            if (" + allw + ") {\n");
+                for (size_t r = 0; r < rds.size(); ++r) {
+                    const Rd &R = rds[r];
+                    const std::string slot =
+                        "Q" + std::to_string(R.grp) + "_" + std::to_string(R.dz - grps[R.grp].dzlo);
+                    const std::string valid =
+                        "W" + std::to_string(R.grp) + "_" + std::to_string(R.dz - grps[R.grp].dzlo);
+                    if (std::abs(R.dx) > V) {
+                        b << "#pragma unroll\n"
+                          << "                for (int j = 0; j < V; ++j) " << R.dst << "[j] = f" << r << "[j];\n";
+                        continue;
+                    }
+                    b << "                {\n";
+                    if (R.dx != 0)
+                        b << "                    const unsigned long long mne = __builtin_amdgcn_ballot_w64(ne" << r
+                          << ");\n";
+                    for (int j = 0; j < V; ++j) {
+                        const int e = j + R.dx;
+                        std::string src;
+                        if (e < 0)
+                            src = "dcp_dpp<DCP_LOWER>(" + slot + "[" + std::to_string(e + V) + "])";
+                        else if (e >= V)
+                            src = "dcp_dpp<DCP_UPPER>(" + slot + "[" + std::to_string(e - V) + "])";
+                        else
+                            src = slot + "[" + std::to_string(e) + "]";
+                        std::string c = general ? "(" + valid + " ? " + src + " : " + T + "(0))" : src;
+                        if (e < 0 || e >= V)
+                            c = "dcp_sel(mne, e" + std::to_string(r) + "_" + std::to_string(j) + ", " + c + ")";
+                        if (general) c = "dcp_sel(mrg, g" + std::to_string(r) + "[" + std::to_string(j) + "], " + c + ")";
+                        b << "                    " << R.dst << "[" << j << "] = " << c << ";\n";
+                    }
+                    b << "                }\n";
+                }
+            }
+            b << "            }\n";
             b << "            " << K.fname << "_comp<I>(" << params_pass.str() << ", i, x, nx" << rd_pass.str()
               << ");\n";
             // the queues move up one plane
