@@ -260,3 +260,34 @@ def test_grid_beyond_32_bit_indices_sampled():
         del out
     del u, f
     torch.cuda.empty_cache()
+
+
+def adjoint_step_program(dtype="f64", h=1.0):
+    # the transposed step Jacobian applied to lambda: the Laplacian is
+    # symmetric, so lambda + dt*(alpha*Lap7(lambda) - 3*beta*u^2*lambda)
+    F = _fuse()
+    P = F.Program(dtype)
+    lam, u = P.input("lam", "u")
+    alpha, beta, dt = P.param("alpha", "beta", "dt")
+    P.output("lam_prev", lam + dt * (alpha * F.lap7(lam, h) - (3.0 * beta) * ((u * u) * lam)))
+    return P
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_generated_adjoint_step(bc):
+    # a second program of the method: bit for bit the interpreter, and one
+    # step of the C oracle's adjoint (T = 1: dL/du0 = J^T lambda_1) within
+    # the FP64 tolerance (the oracle scatters L^T, a different rounding order)
+    P = adjoint_step_program()
+    prog = P.compile()
+    assert prog.n_kernels == 1
+    shape = (37, 23, 19)
+    u0, f = rand_fields(shape, 1300 + bc)
+    seed, _ = rand_fields(shape, 1302 + bc)
+    prm = {k: BASE[k] for k in ("alpha", "beta", "dt")}
+    say("fuse adjoint step", bc)
+    (got,) = run_gpu(prog, [seed, u0], prm, bc)
+    (want,) = fuse_interp.run(P.text(), [seed, u0], prm, bc)
+    assert np.array_equal(got, want)
+    g_u0, _, _ = oracle.adjoint(u0, f, seed, BASE, 1, bc)
+    assert np.max(np.abs(got - g_u0)) / np.max(np.abs(g_u0)) <= 1e-12
