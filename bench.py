@@ -17,8 +17,9 @@ In the same run (--forms all, the default) every other form of the metric
 is timed on the same inputs, each in its own event-timed region: the
 unfused single-operator chain, the float32 forms, the adjoint kernel and
 the end-to-end gradient (forward with checkpoints + checkpointed adjoint);
-one step run by kernels the fusing compiler generates (fused, and one
-kernel per statement) beside the hand-written one-step kernels; then the two
+one step (and one adjoint step) run by kernels the fusing compiler
+generates (fused, and one kernel per statement) beside the hand-written
+one-step kernels; then the two
 Jacobi listings (jacobi_1d, jacobi_2d) at the paper's problem sizes and
 weak-scaled to 1296 processes, with and without temporal blocking.
 
@@ -211,6 +212,17 @@ def step_program(dtype: str, h: float):
     return P
 
 
+def adjoint_step_program(dtype: str, h: float):
+    """The adjoint step lambda + dt*(alpha*Lap7(lambda) - 3*beta*u^2*lambda)
+    as a single-operator program (the Laplacian is symmetric)."""
+    from paper_2107_00555_amd import fuse
+    P = fuse.Program(dtype)
+    lam, u = P.input("lam", "u")
+    alpha, beta, dt = P.param("alpha", "beta", "dt")
+    P.output("lam_prev", lam + dt * (alpha * fuse.lap7(lam, h) - (3.0 * beta) * ((u * u) * lam)))
+    return P
+
+
 def program_bytes_unfused(text: str, S: int) -> int:
     """Per-point algorithmic bytes of the unfused program: every field
     statement reads its field operands and writes its result."""
@@ -270,6 +282,25 @@ def generated_forms(args, dev, stream, u0, f64, coeffs, bc) -> dict:
         ent["generated_fused_vs_handwritten_fused"] = round(ent["handwritten_fused"]["ms"] /
                                                              ent["generated_fused"]["ms"], 3)
         gen[f"step_{dname}"] = ent
+        # the adjoint step, the method's second expression (no hand-written
+        # counterpart: the library's adjoint kernel also forms the parameter sums)
+        A = adjoint_step_program(dname, coeffs["h"])
+        aprm = {k: coeffs[k] for k in ("alpha", "beta", "dt")}
+        ent_a = {}
+        for label, fuse in (("generated_fused", True), ("generated_unfused", False)):
+            prog = A.compile(fuse=fuse)
+            ws = api.workspace(prog.workspace_bytes(tuple(u.shape)), dev)
+            log(f"timing adjoint step {label} {dname} ({prog.n_kernels} kernels)")
+            ms, _, _ = timed(lambda: prog.run([f, u], aprm, bc=bc, outputs=[out], ws=ws), k, 2, stream)
+            ms /= k
+            bpp = 3 * S if fuse else program_bytes_unfused(A.text(), S)
+            ent_a[label] = {"kernels": prog.n_kernels, "ms": round(ms, 4), "glups": round(N / (ms * 1e-3) / 1e9, 3),
+                            "bytes_per_point": bpp,
+                            "hbm_frac": round(bpp * N / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            del prog, ws
+        ent_a["generated_fused_over_unfused"] = round(ent_a["generated_unfused"]["ms"] /
+                                                      ent_a["generated_fused"]["ms"], 2)
+        gen[f"adjoint_step_{dname}"] = ent_a
         del u, f, out
         torch.cuda.empty_cache()
     return gen
