@@ -115,3 +115,46 @@ def test_random_programs_compile_with_torch_loaded(F, seed, dtype):
         prog = P.compile(fuse)
         assert prog.n_kernels >= 1
         assert "asm" not in prog.source
+
+
+def test_run_argument_checks_on_the_host(F):
+    # every case below is rejected before any device call (placeholder
+    # addresses are never dereferenced); an empty grid is a no-op.  Run only
+    # where no GPU is visible, so a regression could never reach a launch
+    import ctypes
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("placeholder device addresses: host-only check")
+    L = F._load()
+    P = step_program(F)                                  # 2 inputs, 4 params, 1 output
+    p = P.compile()
+    vp = ctypes.c_void_p
+    ins = (vp * 2)(0x10000, 0x20000)
+    outs = (vp * 1)(0x30000)
+    prm = (ctypes.c_double * 4)(1.0, 0.1, 0.5, 0.1)
+    h = p._h
+
+    def run(i=ins, q=prm, o=outs, n=(8, 8, 8), bc=1, ws=None, wsb=0):
+        return L.dcp_fuse_run(h, i, q, o, n[0], n[1], n[2], bc, ws, wsb, None)
+
+    assert run(n=(0, 8, 8)) == 0 and run(i=None, q=None, o=None, n=(8, 0, 8)) == 0   # empty grid
+    assert run(n=(-1, 8, 8)) == -2
+    assert run(n=(1 << 40, 1 << 20, 8)) == -2                                        # size overflows
+    assert run(bc=2) == -4
+    assert run(i=None) == -1 and run(o=None) == -1 and run(q=None) == -1
+    assert run(i=(vp * 2)(0x10000, None)) == -1
+    nan = (ctypes.c_double * 4)(1.0, float("nan"), 0.5, 0.1)
+    assert run(q=nan) == -5
+    # the output overlaps an input (8^3 float64 = 4096 bytes from each address)
+    assert run(o=(vp * 1)(0x10000 + 4088)) == -7
+    # a program with a stored temporary needs a workspace
+    Q = F.Program("f64")
+    (u,) = Q.input("u")
+    Q.output("y", (u * u).shift(1, 0, 0))
+    q2 = Q.compile()
+    need = q2.workspace_bytes((8, 8, 8))
+    assert need == 4096
+    one = (vp * 1)(0x10000)
+    assert L.dcp_fuse_run(q2._h, one, None, outs, 8, 8, 8, 1, None, 0, None) == -1
+    assert L.dcp_fuse_run(q2._h, one, None, outs, 8, 8, 8, 1, vp(0x80000), need - 1, None) == -6
+    assert L.dcp_fuse_run(q2._h, one, None, outs, 8, 8, 8, 1, vp(0x30000 + 256), need, None) == -7
