@@ -107,8 +107,8 @@ class Program:
     def text(self) -> str:
         return "\n".join(self.lines) + "\n"
 
-    def compile(self, fuse: bool = True) -> "Fused":
-        return compile_text(self.text(), fuse)
+    def compile(self, fuse: bool = True, cache: bool = True) -> "Fused":
+        return compile_text(self.text(), fuse, cache)
 
 
 def _load():
@@ -136,14 +136,29 @@ class FuseError(ValueError):
     pass
 
 
-def compile_text(text: str, fuse: bool = True) -> "Fused":
+_CACHE: dict = {}
+_CACHE_MAX = 64
+
+
+def compile_text(text: str, fuse: bool = True, cache: bool = True) -> "Fused":
+    """Builds (parses, partitions, generates, compiles) a program.  The same
+    text and mode compiled again in this process returns the same object
+    (run-time compilation takes about a second); cache=False forces a build."""
+    key = (text, bool(fuse))
+    if cache and key in _CACHE:
+        return _CACHE[key]
     L = _load()
     h = ctypes.c_void_p()
     err = ctypes.create_string_buffer(4096)
     rc = L.dcp_fuse_build(text.encode(), int(bool(fuse)), ctypes.byref(h), err, len(err))
     if rc != 0:
         raise FuseError(f"dcp_fuse_build: {err.value.decode()} (status {rc})")
-    return Fused(h, text)
+    prog = Fused(h, text)
+    if cache:
+        if len(_CACHE) >= _CACHE_MAX:
+            _CACHE.pop(next(iter(_CACHE)))        # the oldest entry
+        _CACHE[key] = prog
+    return prog
 
 
 class Fused:

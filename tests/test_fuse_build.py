@@ -158,3 +158,12 @@ def test_run_argument_checks_on_the_host(F):
     assert L.dcp_fuse_run(q2._h, one, None, outs, 8, 8, 8, 1, None, 0, None) == -1
     assert L.dcp_fuse_run(q2._h, one, None, outs, 8, 8, 8, 1, vp(0x80000), need - 1, None) == -6
     assert L.dcp_fuse_run(q2._h, one, None, outs, 8, 8, 8, 1, vp(0x30000 + 256), need, None) == -7
+
+
+def test_compile_cache(F):
+    P = step_program(F)
+    a = P.compile()
+    assert P.compile() is a                              # same text and mode: the same program
+    assert P.compile(fuse=False) is not a
+    b = P.compile(cache=False)
+    assert b is not a and b.n_kernels == a.n_kernels and b.source == a.source

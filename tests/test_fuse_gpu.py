@@ -186,7 +186,7 @@ def test_free_right_after_a_run():
     u, fd = to_dev(u0, torch.float32), to_dev(f, torch.float32)
     out = torch.empty_like(u)
     say("fuse free after run")
-    prog = P.compile()
+    prog = P.compile(cache=False)                       # the only reference
     prog.run([u, fd], PARAMS, bc=0, outputs=[out])
     del prog
     torch.cuda.synchronize()
