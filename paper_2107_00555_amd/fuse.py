@@ -201,16 +201,25 @@ class Fused:
 
     def run(self, inputs, params=None, bc="dirichlet0", outputs=None, ws=None):
         """inputs: tensors in declaration order (shape (nz, ny, nx), the
-        program's dtype, contiguous, on the GPU); params: dict or sequence.
-        Returns the list of output tensors."""
+        program's dtype, contiguous, on one GPU); params: dict or sequence;
+        outputs: tensors like the inputs (allocated when None); ws: a byte
+        workspace (allocated when None or too small).  Runs on the inputs'
+        device and its current stream.  Returns the list of output tensors."""
         from .api import bc_code
-        if len(inputs) != self.n_inputs:
+        if len(inputs) != self.n_inputs or self.n_inputs == 0:
             raise ValueError(f"expected {self.n_inputs} inputs")
+        dev = inputs[0].device
+
+        def check(t, what):
+            if (not isinstance(t, torch.Tensor) or t.dtype != self.dtype or not t.is_contiguous()
+                    or t.device != dev or t.dim() != 3 or t.shape != inputs[0].shape):
+                raise ValueError(f"{what}: contiguous 3-D tensors of the program's dtype, of one shape, "
+                                 "on one GPU")
+
+        if dev.type != "cuda":
+            raise ValueError("inputs must be on a GPU")
         for t in inputs:
-            if t.dtype != self.dtype or not t.is_contiguous() or t.device.type != "cuda" or t.dim() != 3:
-                raise ValueError("inputs: contiguous 3-D GPU tensors of the program's dtype")
-            if t.shape != inputs[0].shape:
-                raise ValueError("inputs must share one shape")
+            check(t, "inputs")
         shape = inputs[0].shape
         if isinstance(params, dict):
             params = [params[k] for k in self.params]
@@ -219,15 +228,21 @@ class Fused:
             raise ValueError(f"expected {self.n_params} params")
         if outputs is None:
             outputs = [torch.empty_like(inputs[0]) for _ in range(self.n_outputs)]
+        if len(outputs) != self.n_outputs:
+            raise ValueError(f"expected {self.n_outputs} outputs")
+        for t in outputs:
+            check(t, "outputs")
         wsb = self.workspace_bytes(shape)
-        if wsb and (ws is None or ws.numel() < wsb):
-            ws = torch.empty(wsb, dtype=torch.uint8, device=inputs[0].device)
-        ip = (ctypes.c_void_p * max(1, len(inputs)))(*[t.data_ptr() for t in inputs])
-        op = (ctypes.c_void_p * max(1, len(outputs)))(*[t.data_ptr() for t in outputs])
+        if wsb and (ws is None or ws.device != dev or not ws.is_contiguous()
+                    or ws.numel() * ws.element_size() < wsb):
+            ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+        ip = (ctypes.c_void_p * len(inputs))(*[t.data_ptr() for t in inputs])
+        op = (ctypes.c_void_p * len(outputs))(*[t.data_ptr() for t in outputs])
         pp = (ctypes.c_double * max(1, len(params)))(*[float(v) for v in params])
         nz, ny, nx = shape
-        stream = ctypes.c_void_p(torch.cuda.current_stream(inputs[0].device).cuda_stream)
-        _lib.check("dcp_fuse_run", _load().dcp_fuse_run(
-            self._h, ip, pp, op, nx, ny, nz, bc_code(bc),
-            ctypes.c_void_p(ws.data_ptr()) if wsb else None, wsb, stream))
+        with torch.cuda.device(dev):
+            stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+            _lib.check("dcp_fuse_run", _load().dcp_fuse_run(
+                self._h, ip, pp, op, nx, ny, nz, bc_code(bc),
+                ctypes.c_void_p(ws.data_ptr()) if wsb else None, wsb, stream))
         return outputs

@@ -142,6 +142,15 @@ def test_run_argument_errors():
         prog.run([u, u.clone()], PARAMS, outputs=[u])   # output aliases an input
     with pytest.raises(_lib.DcpError):
         prog.run([u, u.clone()], dict(PARAMS, alpha=float("nan")))
+    # outputs are checked before anything is launched
+    with pytest.raises(ValueError):
+        prog.run([u, u.clone()], PARAMS, outputs=[torch.zeros((4, 4, 3), dtype=torch.float64, device=DEV)])
+    with pytest.raises(ValueError):
+        prog.run([u, u.clone()], PARAMS, outputs=[torch.zeros((4, 4, 4), dtype=torch.float32, device=DEV)])
+    with pytest.raises(ValueError):
+        prog.run([u, u.clone()], PARAMS, outputs=[])
+    with pytest.raises(ValueError):
+        prog.run([u, u.clone()], PARAMS, outputs=[torch.zeros((4, 4, 8), dtype=torch.float64, device=DEV)[:, :, ::2]])
 
 
 def test_two_threads_share_one_program():
