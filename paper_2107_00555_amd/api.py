@@ -69,6 +69,15 @@ def workspace(nbytes: int, device) -> torch.Tensor | None:
     return torch.empty(nbytes, dtype=torch.uint8, device=device)
 
 
+def _ws(ws, nbytes: int, device) -> torch.Tensor | None:
+    """The caller's workspace if it is a contiguous tensor on the device with
+    at least nbytes bytes, else a new one."""
+    if (isinstance(ws, torch.Tensor) and ws.device == torch.device(device) and ws.is_contiguous()
+            and ws.numel() * ws.element_size() >= nbytes):
+        return ws
+    return workspace(nbytes, device)
+
+
 def num_slots(T: int, k: int) -> int:
     return 0 if T <= 0 else (T + k - 1) // k
 
@@ -92,8 +101,9 @@ def step(u: torch.Tensor, f: torch.Tensor, coeffs, bc, impl="fused", norms: bool
     ws = workspace(wsb, u.device)
     n2 = torch.empty(2, dtype=torch.float64, device=u.device) if norms else None
     fn = _lib.lib().dcp_step_fused if ic == FUSED else _lib.lib().dcp_step_unfused
-    _lib.check(fn.__name__, fn(dt, _ptr(u), _ptr(f), _ptr(out), nx, ny, nz, ctypes.byref(c),
-                               bc_code(bc), _ptr(n2), _ptr(ws), wsb, _stream(u.device)))
+    with torch.cuda.device(u.device):
+        _lib.check(fn.__name__, fn(dt, _ptr(u), _ptr(f), _ptr(out), nx, ny, nz, ctypes.byref(c),
+                                   bc_code(bc), _ptr(n2), _ptr(ws), wsb, _stream(u.device)))
     return out, n2
 
 
@@ -114,17 +124,17 @@ def run(u: torch.Tensor, f: torch.Tensor, coeffs, T: int, bc, impl="fused", tblo
     if tblock is None:
         tblock = 2 if ic == FUSED else 1
     wsb = _lib.workspace_bytes(OP_RUN, dt, nx, ny, nz, T=T, tblock=tblock, norms=norms, impl=ic)
-    if ws is None or ws.numel() < wsb:
-        ws = workspace(wsb, u.device)
+    ws = _ws(ws, wsb, u.device)
     energy = torch.empty(max(T, 0), dtype=torch.float64, device=u.device) if norms else None
     resid = torch.empty(max(T, 0), dtype=torch.float64, device=u.device) if norms else None
     if ckpt_every and ckpt is None:
         ckpt = torch.empty((num_slots(T, ckpt_every), nz, ny, nx), dtype=u.dtype, device=u.device)
     elif not ckpt_every:
         ckpt = None
-    _lib.check("dcp_run", _lib.lib().dcp_run(
-        dt, ic, _ptr(u), _ptr(f), nx, ny, nz, ctypes.byref(c), bc_code(bc), int(T), int(tblock),
-        _ptr(energy), _ptr(resid), _ptr(ckpt), int(ckpt_every), _ptr(ws), wsb, _stream(u.device)))
+    with torch.cuda.device(u.device):
+        _lib.check("dcp_run", _lib.lib().dcp_run(
+            dt, ic, _ptr(u), _ptr(f), nx, ny, nz, ctypes.byref(c), bc_code(bc), int(T), int(tblock),
+            _ptr(energy), _ptr(resid), _ptr(ckpt), int(ckpt_every), _ptr(ws), wsb, _stream(u.device)))
     return {"energy": energy, "resid": resid, "ckpt": ckpt}
 
 
@@ -145,17 +155,17 @@ def adjoint_run(ckpt: torch.Tensor | None, ckpt_every: int, f: torch.Tensor, lam
     c = Coeffs.make(coeffs)
     wsb = _lib.workspace_bytes(OP_ADJOINT, dt, nx, ny, nz, T=T, ckpt_every=ckpt_every, tblock=tblock,
                                norms=want_gamma and not want_f)
-    if ws is None or ws.numel() < wsb:
-        ws = workspace(wsb, lam_T.device)
+    ws = _ws(ws, wsb, lam_T.device)
     if grad_u0 is None:
         grad_u0 = torch.empty_like(lam_T)
     gab = torch.empty(2, dtype=torch.float64, device=lam_T.device)
     gf = torch.empty_like(lam_T) if want_f else None
     gg = torch.empty(1, dtype=torch.float64, device=lam_T.device) if want_gamma else None
-    _lib.check("dcp_adjoint_run", _lib.lib().dcp_adjoint_run(
-        dt, _ptr(ckpt), int(ckpt_every), _ptr(f), _ptr(lam_T), nx, ny, nz, ctypes.byref(c),
-        bc_code(bc), int(T), int(tblock), _ptr(grad_u0), _ptr(gab), _ptr(gf), _ptr(gg), _ptr(ws), wsb,
-        _stream(lam_T.device)))
+    with torch.cuda.device(lam_T.device):
+        _lib.check("dcp_adjoint_run", _lib.lib().dcp_adjoint_run(
+            dt, _ptr(ckpt), int(ckpt_every), _ptr(f), _ptr(lam_T), nx, ny, nz, ctypes.byref(c),
+            bc_code(bc), int(T), int(tblock), _ptr(grad_u0), _ptr(gab), _ptr(gf), _ptr(gg), _ptr(ws), wsb,
+            _stream(lam_T.device)))
     if not (want_f or want_gamma):
         return grad_u0, gab
     out = {"u0": grad_u0, "ab": gab}
@@ -177,9 +187,10 @@ def revolve_forward(u: torch.Tensor, f: torch.Tensor, coeffs, T: int, bc, nslots
     c = Coeffs.make(coeffs)
     wsb = _lib.revolve_workspace_bytes(dt, nx, ny, nz, T, nslots, reserve_sum)
     ws = workspace(wsb, u.device)
-    _lib.check("dcp_revolve_forward", _lib.lib().dcp_revolve_forward(
-        dt, _ptr(u), _ptr(f), nx, ny, nz, ctypes.byref(c), bc_code(bc), int(T), int(nslots), int(tblock),
-        _ptr(ws), wsb, _stream(u.device)))
+    with torch.cuda.device(u.device):
+        _lib.check("dcp_revolve_forward", _lib.lib().dcp_revolve_forward(
+            dt, _ptr(u), _ptr(f), nx, ny, nz, ctypes.byref(c), bc_code(bc), int(T), int(nslots), int(tblock),
+            _ptr(ws), wsb, _stream(u.device)))
     return ws if ws is not None else torch.empty(0, dtype=torch.uint8, device=u.device)
 
 
@@ -192,16 +203,20 @@ def revolve_adjoint(ws: torch.Tensor, f: torch.Tensor, lam_T: torch.Tensor, coef
     nz, ny, nx = lam_T.shape
     c = Coeffs.make(coeffs)
     wsb = _lib.revolve_workspace_bytes(dt, nx, ny, nz, T, nslots, want_gamma and not want_f)
+    if (not isinstance(ws, torch.Tensor) or ws.dtype != torch.uint8 or ws.device != lam_T.device
+            or not ws.is_contiguous()):
+        raise ValueError("ws must be the byte workspace revolve_forward returned, on lam_T's device")
     if ws.numel() < wsb:
         raise ValueError("workspace smaller than this call needs (reserve_sum in revolve_forward?)")
     grad_u0 = torch.empty_like(lam_T)
     gab = torch.empty(2, dtype=torch.float64, device=lam_T.device)
     gf = torch.empty_like(lam_T) if want_f else None
     gg = torch.empty(1, dtype=torch.float64, device=lam_T.device) if want_gamma else None
-    _lib.check("dcp_revolve_adjoint", _lib.lib().dcp_revolve_adjoint(
-        dt, _ptr(f), _ptr(lam_T), nx, ny, nz, ctypes.byref(c), bc_code(bc), int(T), int(nslots), int(tblock),
-        _ptr(grad_u0), _ptr(gab), _ptr(gf), _ptr(gg), _ptr(ws) if ws.numel() else None, ws.numel(),
-        _stream(lam_T.device)))
+    with torch.cuda.device(lam_T.device):
+        _lib.check("dcp_revolve_adjoint", _lib.lib().dcp_revolve_adjoint(
+            dt, _ptr(f), _ptr(lam_T), nx, ny, nz, ctypes.byref(c), bc_code(bc), int(T), int(nslots), int(tblock),
+            _ptr(grad_u0), _ptr(gab), _ptr(gf), _ptr(gg), _ptr(ws) if ws.numel() else None, ws.numel(),
+            _stream(lam_T.device)))
     if not (want_f or want_gamma):
         return grad_u0, gab
     out = {"u0": grad_u0, "ab": gab}
@@ -233,10 +248,10 @@ def jacobi_1d(A: torch.Tensor, B: torch.Tensor, tsteps: int, tblock: int = 0,
     _jacobi_arrays(A, B, 1)
     n = A.shape[0]
     wsb = _lib.jacobi_workspace_bytes(1, n, 1, tsteps, tblock)
-    if ws is None or ws.numel() < wsb:
-        ws = workspace(wsb, A.device)
-    _lib.check("dcp_jacobi_1d", _lib.lib().dcp_jacobi_1d(
-        int(tsteps), _ptr(A), _ptr(B), n, int(tblock), _ptr(ws), wsb, _stream(A.device)))
+    ws = _ws(ws, wsb, A.device)
+    with torch.cuda.device(A.device):
+        _lib.check("dcp_jacobi_1d", _lib.lib().dcp_jacobi_1d(
+            int(tsteps), _ptr(A), _ptr(B), n, int(tblock), _ptr(ws), wsb, _stream(A.device)))
     return A, B
 
 
@@ -246,8 +261,8 @@ def jacobi_2d(A: torch.Tensor, B: torch.Tensor, tsteps: int, tblock: int = 0,
     _jacobi_arrays(A, B, 2)
     n0, n1 = A.shape
     wsb = _lib.jacobi_workspace_bytes(2, n0, n1, tsteps, tblock)
-    if ws is None or ws.numel() < wsb:
-        ws = workspace(wsb, A.device)
-    _lib.check("dcp_jacobi_2d", _lib.lib().dcp_jacobi_2d(
-        int(tsteps), _ptr(A), _ptr(B), n0, n1, int(tblock), _ptr(ws), wsb, _stream(A.device)))
+    ws = _ws(ws, wsb, A.device)
+    with torch.cuda.device(A.device):
+        _lib.check("dcp_jacobi_2d", _lib.lib().dcp_jacobi_2d(
+            int(tsteps), _ptr(A), _ptr(B), n0, n1, int(tblock), _ptr(ws), wsb, _stream(A.device)))
     return A, B
