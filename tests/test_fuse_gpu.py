@@ -300,3 +300,27 @@ def test_generated_adjoint_step(bc):
     assert np.array_equal(got, want)
     g_u0, _, _ = oracle.adjoint(u0, f, seed, BASE, 1, bc)
     assert np.max(np.abs(got - g_u0)) / np.max(np.abs(g_u0)) <= 1e-12
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_full_size_step_sampled(dtype):
+    # the benchmark's configuration: the step program on the 512^3 periodic
+    # workload (seeded fields), one generated kernel; 300 sampled points
+    # (faces, edges, corners, the interior) against the per-point interpreter
+    from paper_2107_00555_amd import inputs
+    u0, f = inputs.make_fields("fwd_512_f64", seed=0)
+    dt = np.float64 if dtype == "f64" else np.float32
+    u0, f = u0.astype(dt), f.astype(dt)
+    P = step_program(dtype)
+    prog = P.compile()
+    say("fuse full size", dtype)
+    (out,) = prog.run([to_dev(u0, prog.dtype), to_dev(f, prog.dtype)], PARAMS, bc=1)
+    torch.cuda.synchronize()
+    n = 512
+    r = np.random.default_rng(5)
+    edge = [0, 1, n - 2, n - 1]
+    pts = [(z, y, x) for z in edge for y in edge for x in edge]
+    pts += [tuple(int(v) for v in r.integers(0, n, 3)) for _ in range(300 - len(pts))]
+    want = fuse_interp.run_points(P.text(), [u0, f], PARAMS, 1, pts)[0]
+    got = np.array([out[z, y, x].item() for z, y, x in pts], dtype=dt)
+    assert np.array_equal(got, want)
