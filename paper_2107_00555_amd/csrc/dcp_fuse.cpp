@@ -310,8 +310,9 @@ std::string scalar_expr(const dcp_fused *p, int i, const char *T) {
 
 // Generated code.  A lane computes V consecutive x-points (16 bytes of the
 // dtype); a wave covers 64*V consecutive x of one (y, z) row (a wave tile)
-// and walks zr planes; a workgroup takes four consecutive wave tiles.  y and
-// z are uniform over a wave.  The index type is 32-bit when the grid allows
+// and walks zr planes; a workgroup takes the same x tile of four
+// consecutive rows (a wave's y-neighbour rows are its siblings' rows, so
+// they tend to hit the CU's cache).  y and z are uniform over a wave.  The index type is 32-bit when the grid allows
 // it (a second entry point uses 64-bit indices).
 //
 // Reads of a memory field are grouped by (field, dy).  A group keeps, in
@@ -672,7 +673,7 @@ void generate(dcp_fused *p) {
               << params_decl.str() << ", int zr, i64 tiles_x_, i64 nchunk_) {\n"
               << "    typedef " << I << " I;\n"
               << "    const I nx = (I)nx_, ny = (I)ny_, nz = (I)nz_, tiles_x = (I)tiles_x_;\n"
-              << "    const I nb = tiles_x * ny * (I)nchunk_, nwg = (nb + 3) / 4;\n"
+              << "    const I nyb = (ny + 3) / 4, nwg = tiles_x * nyb * (I)nchunk_;\n"
               << "    const I G = (I)gridDim.x, bk = (I)blockIdx.x;\n"
               // workgroups go to the 8 XCDs in turn: give each XCD one
               // contiguous range of tiles so row neighbours share its L2
@@ -684,10 +685,11 @@ void generate(dcp_fused *p) {
               // one wrap per axis reaches every neighbour
               << "    const bool fast = nx >= V + " << maxd[0] << " && ny >= " << maxd[1] << " && nz > " << maxd[2]
               << ";\n"
+              // a workgroup's four waves take four consecutive rows of one x
+              // tile, so a wave's y-neighbour rows are its siblings' rows
               << "    for (I L = lb; L < nwg; L += G) {\n"
-              << "        const I wt = L * 4 + wv;\n"
-              << "        if (wt >= nb) continue;\n"
-              << "        const I xt = wt % tiles_x, t = wt / tiles_x, y = t % ny, zb = (t / ny) * (I)zr;\n"
+              << "        const I xt = L % tiles_x, t = L / tiles_x, y = (t % nyb) * 4 + wv, zb = (t / nyb) * (I)zr;\n"
+              << "        if (y >= ny) continue;\n"
               << "        const I x = xt * " << 64 * V << " + lane * V;\n"
               << "        if (x >= nx) continue;\n"
               << "        const I ze = (zb + (I)zr < nz ? zb + (I)zr : nz);\n"
@@ -858,10 +860,10 @@ int dcp_fuse_run(dcp_fused *p, const void *const *inputs, const double *params, 
         return static_cast<char *>(ws) + (size_t)m.buf * align256(fb);
     };
     // wave tiles: 64*V x-points of one row (V points per lane, 16 bytes) over
-    // zr consecutive planes, ordered x tile, then row, then plane chunk; four
-    // per workgroup; a one-dimensional grid of at most 2^20 workgroups
-    // strides over them.  zr doubles, up to 16, while at least 4096
-    // workgroups (16 per CU) remain.
+    // zr consecutive planes; a workgroup takes one x tile of four consecutive
+    // rows, workgroups ordered x tile, then row block, then plane chunk; a
+    // one-dimensional grid of at most 2^20 workgroups strides over them.  zr
+    // doubles, up to 16, while at least 4096 workgroups (16 per CU) remain.
     const int64_t tile_w = p->dtype == DCP_F64 ? 128 : 256;
     int64_t tiles_x = (nx + tile_w - 1) / tile_w;
     int64_t zr = 1;
@@ -871,7 +873,7 @@ int dcp_fuse_run(dcp_fused *p, const void *const *inputs, const double *params, 
         if (v >= 1 && v <= 4096) zr = v;
     }
     int64_t nchunk = (nz + zr - 1) / zr;
-    const unsigned grid = (unsigned)std::min<int64_t>((tiles_x * ny * nchunk + 3) / 4, 1 << 20);
+    const unsigned grid = (unsigned)std::min<int64_t>(tiles_x * ((ny + 3) / 4) * nchunk, 1 << 20);
     int zr32 = (int)zr;
     double smax[3] = {0, 0, 0};  // largest |offset| of any shifted read, per axis
     for (const Node &m : p->nodes)
