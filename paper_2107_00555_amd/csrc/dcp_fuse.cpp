@@ -49,6 +49,8 @@
 
 namespace {
 
+constexpr int kRows = 4;  // waves (rows) per workgroup (8 measured slightly slower)
+
 enum Kind { K_INPUT, K_PARAM, K_CONST, K_ADD, K_SUB, K_MUL, K_DIV, K_NEG, K_COPY, K_SHIFT };
 
 struct Node {
@@ -669,11 +671,11 @@ void generate(dcp_fused *p) {
             }
             b << "        }\n";
 
-            s << "extern \"C\" __global__ void __launch_bounds__(256) " << K.fname << suffix << "("
+            s << "extern \"C\" __global__ void __launch_bounds__(" << 64 * kRows << ") " << K.fname << suffix << "("
               << params_decl.str() << ", int zr, i64 tiles_x_, i64 nchunk_) {\n"
               << "    typedef " << I << " I;\n"
               << "    const I nx = (I)nx_, ny = (I)ny_, nz = (I)nz_, tiles_x = (I)tiles_x_;\n"
-              << "    const I nyb = (ny + 3) / 4, nwg = tiles_x * nyb * (I)nchunk_;\n"
+              << "    const I nyb = (ny + " << kRows - 1 << ") / " << kRows << ", nwg = tiles_x * nyb * (I)nchunk_;\n"
               << "    const I G = (I)gridDim.x, bk = (I)blockIdx.x;\n"
               // workgroups go to the 8 XCDs in turn: give each XCD one
               // contiguous range of tiles so row neighbours share its L2
@@ -688,7 +690,8 @@ void generate(dcp_fused *p) {
               // a workgroup's four waves take four consecutive rows of one x
               // tile, so a wave's y-neighbour rows are its siblings' rows
               << "    for (I L = lb; L < nwg; L += G) {\n"
-              << "        const I xt = L % tiles_x, t = L / tiles_x, y = (t % nyb) * 4 + wv, zb = (t / nyb) * (I)zr;\n"
+              << "        const I xt = L % tiles_x, t = L / tiles_x, y = (t % nyb) * " << kRows
+              << " + wv, zb = (t / nyb) * (I)zr;\n"
               << "        if (y >= ny) continue;\n"
               << "        const I x = xt * " << 64 * V << " + lane * V;\n"
               << "        if (x >= nx) continue;\n"
@@ -873,7 +876,7 @@ int dcp_fuse_run(dcp_fused *p, const void *const *inputs, const double *params, 
         if (v >= 1 && v <= 4096) zr = v;
     }
     int64_t nchunk = (nz + zr - 1) / zr;
-    const unsigned grid = (unsigned)std::min<int64_t>(tiles_x * ((ny + 3) / 4) * nchunk, 1 << 20);
+    const unsigned grid = (unsigned)std::min<int64_t>(tiles_x * ((ny + kRows - 1) / kRows) * nchunk, 1 << 20);
     int zr32 = (int)zr;
     double smax[3] = {0, 0, 0};  // largest |offset| of any shifted read, per axis
     for (const Node &m : p->nodes)
@@ -906,7 +909,7 @@ int dcp_fuse_run(dcp_fused *p, const void *const *inputs, const double *params, 
         args.push_back(&tiles_x);
         args.push_back(&nchunk);
         hipFunction_t fn = fns[2 * k + (idx32 ? 0 : 1)];
-        if (hipModuleLaunchKernel(fn, grid, 1, 1, 256, 1, 1, 0, st, args.data(),
+        if (hipModuleLaunchKernel(fn, grid, 1, 1, 64 * kRows, 1, 1, 0, st, args.data(),
                                   nullptr) != hipSuccess)
             return DCP_E_HIP;
     }
