@@ -76,6 +76,20 @@ __device__ __forceinline__ void tb_copy(T (&d)[VEC], const T (&s)[VEC]) {
     for (int i = 0; i < VEC; ++i) d[i] = s[i];
 }
 
+// The value of lane - 1 (CTRL 0x138, wave_shr:1) or lane + 1 (0x130,
+// wave_shl:1) of the wave; zero at the wave's ends.
+template <int CTRL>
+__device__ __forceinline__ float tb_dpp(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double tb_dpp(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, true);
+    const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 // Coordinate under the boundary rule for any integer i; -1 = ghost (zero).
 template <int BC>
 __device__ __forceinline__ int tb_wrap(int i, int n) {
@@ -140,7 +154,10 @@ __global__ void __launch_bounds__(NT) tb2_kernel(TbArgs a) {
     const int64_t sz = a.nx * a.ny;
     const int CH = nx / VEC;
     T *L0 = reinterpret_cast<T *>(tb_smem);
-    T *L1[2] = {L0 + R0 * nx, L0 + (R0 + R1) * nx};
+    // level-1 buffer b (0 or 1) starts R0 + b*R1 rows into the LDS area; an
+    // offset from L0 (not a pointer picked from an array) keeps every access
+    // an LDS instruction
+    auto L1 = [&](int b) -> T * { return L0 + (R0 + (b & 1) * R1) * nx; };
 
     const int tid = threadIdx.x;
     const int L = tb_xcd_remap(blockIdx.x, gridDim.x);
@@ -219,6 +236,17 @@ __global__ void __launch_bounds__(NT) tb2_kernel(TbArgs a) {
         if constexpr (BC == 1) return base[o - xo];
         return T(0);
     };
+    // The neighbouring chunks of a row are held by the neighbouring lanes
+    // (chunk idx - 1 by lane - 1, idx + 1 by lane + 1, in the same stage), so
+    // the x-neighbours come across the wave; the first and last lane of a
+    // wave and the chunks at a row's ends read them from LDS.
+    const int wlane = tid & 63;
+    auto xnbrs = [&](const T *base, int o, int xo, const T (&c)[VEC], T &lft, T &rgt) {
+        const T fl = tb_dpp<0x138>(c[VEC - 1]);
+        const T fu = tb_dpp<0x130>(c[0]);
+        lft = (wlane != 0 && xo > 0) ? fl : xleft(base, o, xo);
+        rgt = (wlane != 63 && xo + VEC < nx) ? fu : xright(base, o, xo);
+    };
 
     // register queues: level 0 at q-1, q+1 and the prefetched q+2; level 1 at
     // q-2 and q; level-1 point operand at q and the prefetched q+1; level-2
@@ -258,7 +286,7 @@ __global__ void __launch_bounds__(NT) tb2_kernel(TbArgs a) {
         // stage A: level 1 at plane q
         const int qr = tb_wrap<BC>(q, nz);
         const bool owned_plane = q >= z0 && q < z1;
-        T *L1w = L1[q & 1];
+        T *L1w = L1(q);
 #pragma unroll
         for (int k = 0; k < kTbKmax; ++k) {
             if (!(flags[k] & 2u)) continue;
@@ -273,7 +301,8 @@ __global__ void __launch_bounds__(NT) tb2_kernel(TbArgs a) {
                 T ym[VEC], yp[VEC];
                 tb_load<T, VEC>(ym, L0 + o - nx);
                 tb_load<T, VEC>(yp, L0 + o + nx);
-                const T lft = xleft(L0, o, xo), rgt = xright(L0, o, xo);
+                T lft, rgt;
+                xnbrs(L0, o, xo, c, lft, rgt);
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) {
                     const T xm = e == 0 ? lft : c[e > 0 ? e - 1 : 0];
@@ -310,7 +339,7 @@ __global__ void __launch_bounds__(NT) tb2_kernel(TbArgs a) {
 
         // stage B: level 2 at plane q-1, from level 1 at q-2, q-1, q
         if (q - 1 >= z0) {
-            const T *L1r = L1[(q - 1) & 1];
+            const T *L1r = L1(q - 1);
 #pragma unroll
             for (int k = 0; k < kTbKmax; ++k) {
                 if (!(flags[k] & 4u)) continue;
@@ -320,7 +349,8 @@ __global__ void __launch_bounds__(NT) tb2_kernel(TbArgs a) {
                 tb_load<T, VEC>(c, L1r + o);
                 tb_load<T, VEC>(ym, L1r + o - nx);
                 tb_load<T, VEC>(yp, L1r + o + nx);
-                const T lft = xleft(L1r, o, xo), rgt = xright(L1r, o, xo);
+                T lft, rgt;
+                xnbrs(L1r, o, xo, c, lft, rgt);
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) {
                     const T xm = e == 0 ? lft : c[e > 0 ? e - 1 : 0];
@@ -365,7 +395,7 @@ __global__ void __launch_bounds__(NT) tb2_kernel(TbArgs a) {
 #pragma unroll
         for (int k = 0; k < kTbKmax; ++k) {
             if (flags[k] & 1u) tb_load<T, VEC>(am[k], L0 + lofs[k]);
-            if (flags[k] & 2u) tb_load<T, VEC>(bm[k], L1[(q - 1) & 1] + lofs[k] - nx);
+            if (flags[k] & 2u) tb_load<T, VEC>(bm[k], L1(q - 1) + lofs[k] - nx);
         }
         __syncthreads();
 #pragma unroll
