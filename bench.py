@@ -89,19 +89,28 @@ def bootstrap_ci(xs, reps=2000, seed=0):
 
 def timed(fn, k, w, stream):
     """W untimed calls, then K calls with an event between each; returns
-    (total_ms by events, per-call ms list, wall seconds)."""
+    (total_ms by events, per-call ms list, wall seconds).  Python's garbage
+    collector is switched off for the timed calls only: a collection pass
+    there would show up as idle GPU time."""
+    import gc
     import torch
     for _ in range(w):
         fn()
     torch.cuda.synchronize()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(k + 1)]
-    t0 = time.perf_counter()
-    ev[0].record(stream)
-    for i in range(k):
-        fn()
-        ev[i + 1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    was_enabled = gc.isenabled()
+    gc.disable()
+    try:
+        t0 = time.perf_counter()
+        ev[0].record(stream)
+        for i in range(k):
+            fn()
+            ev[i + 1].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    finally:
+        if was_enabled:
+            gc.enable()
     per = [ev[i].elapsed_time(ev[i + 1]) for i in range(k)]
     return ev[0].elapsed_time(ev[k]), per, wall
 
