@@ -8,9 +8,10 @@
 // only within distance 1, and step t+1 is recomputed on a one-row halo.
 //
 // Layout of the work:
-//   * a workgroup (1024 lanes, one per CU) owns full x-rows: a slab of TY
-//     rows x all nx points x zc planes, so there is no x-halo at all and the
-//     periodic x-wrap stays inside the slab;
+//   * a workgroup (512 lanes with four 16-byte chunks each, or 1024 with
+//     two; one workgroup per CU) owns full x-rows: a slab of TY rows x all
+//     nx points x zc planes, so there is no x-halo at all and the periodic
+//     x-wrap stays inside the slab;
 //   * the grid has one workgroup per CU (256), so every slab of a z-run is
 //     resident at once and neighbouring slabs march up z together; their
 //     two-row y-halos are read while the neighbour reads the same rows, and
