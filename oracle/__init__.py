@@ -24,6 +24,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRCS = [os.path.join(_HERE, "rd3d_oracle.c"), os.path.join(_HERE, "jacobi_oracle.c")]
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
+# void cb(int t, const double *u_t, double e_t, double r_t, void *ctx)
+_STEP_CB = ctypes.CFUNCTYPE(None, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_double,
+                            ctypes.c_double, ctypes.c_void_p)
 
 DIRICHLET0 = 0
 PERIODIC = 1
@@ -54,6 +57,9 @@ def _load():
         lib.oracle_run.argtypes = [i64, i64, i64, dp, dp, d, d, d, d, d,
                                    ctypes.c_int, ctypes.c_int, dp, dp, dp]
         lib.oracle_run.restype = ctypes.c_int
+        lib.oracle_run_stream.argtypes = [i64, i64, i64, dp, dp, d, d, d, d, d,
+                                          ctypes.c_int, ctypes.c_int, _STEP_CB, ctypes.c_void_p]
+        lib.oracle_run_stream.restype = ctypes.c_int
         lib.oracle_run_box.argtypes = [i64, i64, i64, dp, dp, d, d, d, d, d,
                                        ctypes.c_int, ctypes.c_int, i64p, i64p, dp]
         lib.oracle_run_box.restype = ctypes.c_int
@@ -109,6 +115,38 @@ def run(u0, f, coeffs: dict, T: int, bc: int, norms: bool = True):
     if rc != 0:
         raise ValueError(f"oracle_run failed with code {rc}")
     return uT, e, r
+
+
+def run_stream(u0, f, coeffs: dict, T: int, bc: int, observe) -> None:
+    """The same T steps as run(), calling ``observe(t, u_t, E_t, R_t)`` after
+    every step t = 1..T.  ``u_t`` is a read-only view of the oracle's own
+    buffer, valid during the call only (copy it to keep it).  An exception
+    raised by ``observe`` is re-raised once the run has finished."""
+    u0 = _field(u0)
+    f = _field(f)
+    if f.shape != u0.shape:
+        raise ValueError("u0 and f must have the same shape")
+    shape = u0.shape
+    errors = []
+
+    def _cb(t, p, e, r, _ctx):
+        if errors:
+            return
+        try:
+            view = np.ctypeslib.as_array(p, shape=shape)
+            view.flags.writeable = False
+            observe(int(t), view, float(e), float(r))
+        except BaseException as exc:  # noqa: BLE001 -- handed back to the caller
+            errors.append(exc)
+
+    cb = _STEP_CB(_cb)
+    nz, ny, nx = shape
+    rc = _load().oracle_run_stream(nx, ny, nz, _ptr(u0), _ptr(f), *_coeffs(coeffs),
+                                   int(bc), int(T), cb, None)
+    if errors:
+        raise errors[0]
+    if rc != 0:
+        raise ValueError(f"oracle_run_stream failed with code {rc}")
 
 
 def run_box(u0, f, coeffs: dict, T: int, bc: int, lo, hi) -> np.ndarray:

@@ -181,6 +181,17 @@ static int check_common(int64_t nx, int64_t ny, int64_t nz, int bc, int T,
     return ORC_OK;
 }
 
+/* Observer of a streaming run: called once per step with the new state u_t
+ * (valid during the call only) and its two norms. */
+typedef void (*oracle_step_cb)(int t, const double *u_t, double e_t,
+                               double r_t, void *ctx);
+
+static int run_whole_grid(int64_t nx, int64_t ny, int64_t nz, const double *u0,
+                          const double *f, double alpha, double beta,
+                          double gamma, double h, double dt, int bc, int T,
+                          double *uT, double *energy, double *resid,
+                          oracle_step_cb cb, void *ctx);
+
 /*
  * T steps from u0 on the whole grid.
  *   uT     [N]  out: the state after T steps (may be NULL)
@@ -191,6 +202,29 @@ int oracle_run(int64_t nx, int64_t ny, int64_t nz, const double *u0,
                const double *f, double alpha, double beta, double gamma,
                double h, double dt, int bc, int T, double *uT, double *energy,
                double *resid) {
+    return run_whole_grid(nx, ny, nz, u0, f, alpha, beta, gamma, h, dt, bc, T,
+                          uT, energy, resid, NULL, NULL);
+}
+
+/*
+ * The same T steps as oracle_run, handing every state u_1 .. u_T to cb as
+ * soon as it is computed, so that a caller can compare each step with
+ * another evaluation without keeping T fields.  Nothing else differs.
+ */
+int oracle_run_stream(int64_t nx, int64_t ny, int64_t nz, const double *u0,
+                      const double *f, double alpha, double beta,
+                      double gamma, double h, double dt, int bc, int T,
+                      oracle_step_cb cb, void *ctx) {
+    if (!cb) return ORC_E_ARG;
+    return run_whole_grid(nx, ny, nz, u0, f, alpha, beta, gamma, h, dt, bc, T,
+                          NULL, NULL, NULL, cb, ctx);
+}
+
+static int run_whole_grid(int64_t nx, int64_t ny, int64_t nz, const double *u0,
+                          const double *f, double alpha, double beta,
+                          double gamma, double h, double dt, int bc, int T,
+                          double *uT, double *energy, double *resid,
+                          oracle_step_cb cb, void *ctx) {
     int rc = check_common(nx, ny, nz, bc, T, h);
     if (rc) return rc;
     grid_t g = {{nx, ny, nz}, {bc, bc, bc}};
@@ -216,6 +250,7 @@ int oracle_run(int64_t nx, int64_t ny, int64_t nz, const double *u0,
         }
         if (energy) energy[t] = nsum_value(&e);
         if (resid) resid[t] = sqrt(nsum_value(&r));
+        if (cb) cb(t + 1, un, nsum_value(&e), sqrt(nsum_value(&r)), ctx);
     }
     if (uT && n > 0) memcpy(uT, st[T & 1], (size_t)n * sizeof(double));
     free_fields(tmp, T_COUNT);

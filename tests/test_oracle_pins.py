@@ -354,3 +354,28 @@ def test_gamma_f_gradients_zero_steps():
     w = np.random.default_rng(36).uniform(-1, 1, u.shape)
     r = oracle.adjoint_full(u, f, w, BASE, 0, 1)
     assert r["gamma"] == 0.0 and np.all(r["f"] == 0.0)
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_streaming_run_hands_out_the_states_of_the_plain_run(bc):
+    # the per-step observer sees exactly the states and norms run() computes
+    # (the same loop; only the hand-off differs)
+    u, f = _rand((7, 5, 4), 37)
+    T = 5
+    seen = []
+    oracle.run_stream(u, f, BASE, T, bc, lambda t, ut, e, r: seen.append((t, ut.copy(), e, r)))
+    assert [s[0] for s in seen] == list(range(1, T + 1))
+    for t, ut, e, r in seen:
+        want, ew, rw = oracle.run(u, f, BASE, t, bc)
+        assert np.array_equal(ut, want)
+        assert e == ew[-1] and r == rw[-1]
+
+
+def test_streaming_run_reraises_the_observers_error():
+    u, f = _rand((3, 3, 3), 38)
+
+    def boom(t, ut, e, r):
+        if t == 2:
+            raise KeyError("observer")
+    with pytest.raises(KeyError):
+        oracle.run_stream(u, f, BASE, 4, 1, boom)
