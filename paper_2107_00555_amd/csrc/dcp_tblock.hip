@@ -461,8 +461,13 @@ hipError_t tb_launch_t(int op, int bc, bool reduce, bool mid, const TbTile &t, c
         if (bc == 0) DCP_TB(0, SOP_ADJL, true, false);
         else DCP_TB(1, SOP_ADJL, true, false);
     } else if (mid) {
-        if (bc == 0) DCP_TB(0, SOP_FWD, false, true);
-        else DCP_TB(1, SOP_FWD, false, true);
+        if (bc == 0) {
+            if (reduce) DCP_TB(0, SOP_FWD, true, true);
+            else DCP_TB(0, SOP_FWD, false, true);
+        } else {
+            if (reduce) DCP_TB(1, SOP_FWD, true, true);
+            else DCP_TB(1, SOP_FWD, false, true);
+        }
     } else if (bc == 0) {
         if (reduce) DCP_TB(0, SOP_FWD, true, false);
         else DCP_TB(0, SOP_FWD, false, false);

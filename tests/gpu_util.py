@@ -49,3 +49,41 @@ def misaligned_like(a: torch.Tensor) -> torch.Tensor:
     v.copy_(a)
     assert v.data_ptr() % 16 != 0
     return v
+
+
+def progress(config, *a):
+    """Print past pytest's output capture (a long full-size case reports its
+    progress while it runs instead of staying silent for minutes)."""
+    cap = config.pluginmanager.getplugin("capturemanager")
+    if cap is None:
+        say(*a)
+        return
+    with cap.global_and_fixture_disabled():
+        say(*a)
+
+
+def rel_err(a, b) -> float:
+    """Largest |a_i - b_i| / |b_i| over a sequence of scalars."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    if a.size == 0:
+        return 0.0
+    return float(np.max(np.abs(a - b) / np.abs(b)))
+
+
+def assert_rel(name: str, got, want, tol: float) -> float:
+    """Assert max_i |got_i - want_i| / |want_i| <= tol, printing the achieved
+    error (scalars or sequences of scalars)."""
+    err = rel_err(np.atleast_1d(np.asarray(got, dtype=np.float64)),
+                  np.atleast_1d(np.asarray(want, dtype=np.float64)))
+    print(f"{name}: relative error {err:.3e} (bound {tol:.0e})")
+    assert err <= tol, (name, err, tol)
+    return err
+
+
+def assert_normwise(name: str, got: np.ndarray, want: np.ndarray, tol: float) -> float:
+    """Assert the normwise field error max|a-b|/max|b| <= tol, printing it."""
+    err = normwise(got, want)
+    print(f"{name}: normwise error {err:.3e} (bound {tol:.0e})")
+    assert err <= tol, (name, err, tol)
+    return err

@@ -6,7 +6,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_util import BASE, DEV, f32_round, normwise, rand_fields, say, to_dev, to_host
+from gpu_util import BASE, DEV, assert_normwise, assert_rel, f32_round, normwise, rand_fields, say, to_dev, to_host
 from paper_2107_00555_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -37,10 +37,10 @@ def test_adjoint_f64_matches_oracle(shape, T, k, bc):
     say("adjoint f64", shape, T, k, bc)
     g, gab = gpu_grad(u0, f, lam, T, bc, k)
     torch.cuda.synchronize()
-    assert normwise(to_host(g), want) <= 1e-12
+    assert_normwise("dL/du0", to_host(g), want, 1e-12)
     gab = to_host(gab)
-    assert gab[0] == pytest.approx(wa, rel=1e-11)
-    assert gab[1] == pytest.approx(wb, rel=1e-11)
+    assert_rel("dL/dalpha", gab[0], wa, 1e-12)
+    assert_rel("dL/dbeta", gab[1], wb, 1e-12)
 
 
 @pytest.mark.parametrize("bc", [0, 1])
@@ -144,8 +144,8 @@ def test_rd3d_backward_matches_oracle():
     loss.backward()
     assert float(loss.detach()) == pytest.approx(loss_w, rel=1e-12)
     assert normwise(to_host(u.grad), gw) <= 1e-12
-    assert float(alpha.grad) == pytest.approx(gaw, rel=1e-11)
-    assert float(beta.grad) == pytest.approx(gbw, rel=1e-11)
+    assert_rel("dL/dalpha", float(alpha.grad), gaw, 1e-12)
+    assert_rel("dL/dbeta", float(beta.grad), gbw, 1e-12)
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
@@ -179,7 +179,7 @@ def test_two_step_adjoint_matches_oracle(bc):
     say("two-step adjoint vs oracle", bc)
     g, gab = gpu_grad(u0, f, lam, T, bc, k)
     torch.cuda.synchronize()
-    assert normwise(to_host(g), want) <= 1e-12
+    assert_normwise("dL/du0", to_host(g), want, 1e-12)
     gab = to_host(gab)
-    assert gab[0] == pytest.approx(wa, rel=1e-11)
-    assert gab[1] == pytest.approx(wb, rel=1e-11)
+    assert_rel("dL/dalpha", gab[0], wa, 1e-12)
+    assert_rel("dL/dbeta", gab[1], wb, 1e-12)

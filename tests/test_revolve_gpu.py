@@ -8,7 +8,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_util import BASE, DEV, normwise, rand_fields, say, to_dev, to_host
+from gpu_util import BASE, DEV, assert_rel, normwise, rand_fields, say, to_dev, to_host
 from paper_2107_00555_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -60,9 +60,9 @@ def test_revolve_matches_oracle(bc):
     assert normwise(to_host(r["u0"]), want["u0"]) <= 1e-12
     assert normwise(to_host(r["f"]), want["f"]) <= 1e-12
     ab = to_host(r["ab"])
-    assert ab[0] == pytest.approx(want["alpha"], rel=1e-11)
-    assert ab[1] == pytest.approx(want["beta"], rel=1e-11)
-    assert float(r["gamma"]) == pytest.approx(want["gamma"], rel=1e-11)
+    assert_rel("dL/dalpha", ab[0], want["alpha"], 1e-12)
+    assert_rel("dL/dbeta", ab[1], want["beta"], 1e-12)
+    assert_rel("dL/dgamma", float(r["gamma"]), want["gamma"], 1e-12)
 
 
 def test_revolve_adjoint_needs_a_fresh_forward():
