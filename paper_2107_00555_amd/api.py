@@ -82,6 +82,28 @@ def num_slots(T: int, k: int) -> int:
     return 0 if T <= 0 else (T + k - 1) // k
 
 
+def check_ckpt(ckpt, T: int, k: int, like: torch.Tensor) -> torch.Tensor:
+    """The checkpoint store of a T-step run with a checkpoint every k steps:
+    a contiguous tensor of num_slots(T, k) fields shaped like `like` (the
+    state), with its dtype and on its device.  The library writes (dcp_run)
+    or reads (dcp_adjoint_run) exactly that many fields through the pointer,
+    so anything smaller, or of another element type, is refused here."""
+    if not isinstance(ckpt, torch.Tensor):
+        raise TypeError("ckpt must be a torch tensor")
+    if k < 1:
+        raise ValueError(f"ckpt_every must be >= 1 when a checkpoint store is used, got {k}")
+    want = (num_slots(T, k),) + tuple(like.shape)
+    if tuple(ckpt.shape) != want:
+        raise ValueError(f"ckpt must be shaped {want} (ceil(T/k) fields), got {tuple(ckpt.shape)}")
+    if ckpt.dtype != like.dtype:
+        raise ValueError(f"ckpt must have the state's dtype {like.dtype}, got {ckpt.dtype}")
+    if ckpt.device != like.device:
+        raise ValueError(f"ckpt must be on the state's device {like.device}, got {ckpt.device}")
+    if not ckpt.is_contiguous():
+        raise ValueError("ckpt must be contiguous")
+    return ckpt
+
+
 def step(u: torch.Tensor, f: torch.Tensor, coeffs, bc, impl="fused", norms: bool = False,
          out: torch.Tensor | None = None):
     """One step u -> u_out.  Returns (u_out, norms2) where norms2 is a float64
@@ -127,10 +149,10 @@ def run(u: torch.Tensor, f: torch.Tensor, coeffs, T: int, bc, impl="fused", tblo
     ws = _ws(ws, wsb, u.device)
     energy = torch.empty(max(T, 0), dtype=torch.float64, device=u.device) if norms else None
     resid = torch.empty(max(T, 0), dtype=torch.float64, device=u.device) if norms else None
-    if ckpt_every and ckpt is None:
+    if ckpt is not None:
+        check_ckpt(ckpt, T, ckpt_every, u)
+    elif ckpt_every:
         ckpt = torch.empty((num_slots(T, ckpt_every), nz, ny, nx), dtype=u.dtype, device=u.device)
-    elif not ckpt_every:
-        ckpt = None
     with torch.cuda.device(u.device):
         _lib.check("dcp_run", _lib.lib().dcp_run(
             dt, ic, _ptr(u), _ptr(f), nx, ny, nz, ctypes.byref(c), bc_code(bc), int(T), int(tblock),
@@ -149,15 +171,17 @@ def adjoint_run(ckpt: torch.Tensor | None, ckpt_every: int, f: torch.Tensor, lam
     dt = _dtype_code(lam_T)
     nz, ny, nx = lam_T.shape
     if T > 0 and lam_T.numel() > 0:
-        if ckpt is None or ckpt.dtype != lam_T.dtype or not ckpt.is_contiguous() \
-                or ckpt.numel() < num_slots(T, ckpt_every) * lam_T.numel():
-            raise ValueError("ckpt must hold ceil(T/ckpt_every) contiguous fields of the state dtype")
+        if ckpt is None:
+            raise ValueError("ckpt (the checkpoints dcp_run wrote) is required for T > 0")
+        check_ckpt(ckpt, T, ckpt_every, lam_T)
     c = Coeffs.make(coeffs)
     wsb = _lib.workspace_bytes(OP_ADJOINT, dt, nx, ny, nz, T=T, ckpt_every=ckpt_every, tblock=tblock,
                                norms=want_gamma and not want_f)
     ws = _ws(ws, wsb, lam_T.device)
     if grad_u0 is None:
         grad_u0 = torch.empty_like(lam_T)
+    else:
+        _field("grad_u0", grad_u0, lam_T)
     gab = torch.empty(2, dtype=torch.float64, device=lam_T.device)
     gf = torch.empty_like(lam_T) if want_f else None
     gg = torch.empty(1, dtype=torch.float64, device=lam_T.device) if want_gamma else None
