@@ -61,6 +61,8 @@ def parse():
                    help="main: the headline only; all: every form; jacobi / generated: the Jacobi "
                         "forms or the fusing compiler's forms only (no headline line; for profiling)")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-errors", action="store_true",
+                   help="skip the per-form error check against the oracle (run after the CPU baseline)")
     p.add_argument("--jacobi-workloads", default="all",
                    help="comma-separated Jacobi workloads to time (names in inputs.JACOBI_WORKLOADS)")
     p.add_argument("--jacobi-no-compare", action="store_true",
@@ -135,18 +137,91 @@ def counter_traffic(tblock):
         return None
 
 
+def cpu_model() -> str | None:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+ORACLE_STEPS = 15
+
+
 def cpu_baseline(u0, f, coeffs, bc):
     """The oracle as it stands, serial, on 15 of the 100 steps of the same
-    512^3 workload (full grid; about 20 s on one host core)."""
+    512^3 workload (full grid; about 20 s on one host core), with the calling
+    thread pinned to one core for the run (the mask is restored afterwards).
+    Returns the baseline entry and the oracle's (u_15, E_t, R_t)."""
     import oracle
-    T = 15
-    t0 = time.perf_counter()
-    oracle.run(u0, f, coeffs, T, bc, norms=True)
-    dt = time.perf_counter() - t0
+    T = ORACLE_STEPS
+    mask = os.sched_getaffinity(0)
+    core = min(mask)
+    os.sched_setaffinity(0, {core})
+    try:
+        t0 = time.perf_counter()
+        uT, e, r = oracle.run(u0, f, coeffs, T, bc, norms=True)
+        dt = time.perf_counter() - t0
+    finally:
+        os.sched_setaffinity(0, mask)
     n = u0.size
-    return {"value": n * T / dt / 1e9, "unit": "GLUP/s", "cores": 1, "kind": "oracle",
+    base = {"value": n * T / dt / 1e9, "unit": "GLUP/s", "cores": 1, "kind": "oracle",
             "sample": f"oracle_run (serial FP64, every temporary materialised) for {T} of the 100 "
-                      f"steps on the full 512^3 periodic grid, {dt:.1f} s"}
+                      f"steps on the full 512^3 periodic grid, {dt:.1f} s, pinned to core {core}",
+            "cpu": {"model": cpu_model(), "nproc": os.cpu_count(), "usable_cores": len(mask)}}
+    return base, (uT, e, r)
+
+
+def form_errors(dev, u0, f64, u0_h, f_h, coeffs, bc, ref64) -> dict:
+    """Error of each GPU form against the oracle after the same 15 steps from
+    u0 on the headline workload: the normwise field error max|a-b|/max|b|
+    and the largest relative error of E_t and R_t over the steps.  float64
+    forms against the oracle run of the CPU baseline; float32 forms against
+    the oracle run on the float32-rounded inputs (run here, untimed)."""
+    import numpy as np
+    import oracle
+    import torch
+
+    from paper_2107_00555_amd import api
+    T = ORACLE_STEPS
+
+    def measure(u, out, ref):
+        uT, e_or, r_or = ref
+        o = torch.from_numpy(uT).to(dev)
+        field = float((u.double() - o).abs().max() / o.abs().max())
+        e = out["energy"].cpu().numpy()
+        r = out["resid"].cpu().numpy()
+        del o
+        return {"field_normwise": field,
+                "energy_max_rel": float(np.max(np.abs(e - e_or) / e_or)),
+                "resid_max_rel": float(np.max(np.abs(r - r_or) / r_or))}
+
+    errs = {"steps": T, "reference": "oracle (FP64, serial) after the same steps from u0"}
+    for name, impl, tb in (("fused_f64_tblock2", "fused", 2), ("fused_f64_tblock1", "fused", 1),
+                           ("unfused_f64", "unfused", 1)):
+        u = u0.clone()
+        out = api.run(u, f64, coeffs, T, bc, impl=impl, tblock=tb, norms=True)
+        torch.cuda.synchronize()
+        errs[name] = measure(u, out, ref64)
+        if impl == "unfused":
+            errs[name]["bitwise_equal"] = bool(torch.equal(u, torch.from_numpy(ref64[0]).to(dev)))
+        del u
+    log("oracle on the float32-rounded inputs (for the float32 errors) ...")
+    u32h = u0_h.astype(np.float32).astype(np.float64)
+    f32h = f_h.astype(np.float32).astype(np.float64)
+    ref32 = oracle.run(u32h, f32h, coeffs, T, bc, norms=True)
+    f32 = f64.to(torch.float32)
+    for tb in (2, 1):
+        u = u0.to(torch.float32)
+        out = api.run(u, f32, coeffs, T, bc, impl="fused", tblock=tb, norms=True)
+        torch.cuda.synchronize()
+        errs[f"fused_f32_tblock{tb}"] = measure(u, out, ref32)
+        del u
+    errs["bounds"] = {"f64": 1e-12, "f32": 1e-5}
+    return errs
 
 
 def jacobi_forms(args, dev, stream) -> dict:
@@ -492,8 +567,12 @@ def main():
             ms_a, _, _ = timed(lambda: api.adjoint_run(ck, 1, ff, lam, coeffs, Ta, bc, ws=wsa, grad_u0=g),
                                kk, 1, stream)
             ms_a /= kk
+            # two adjoint steps per pass (the default): a pass reads lambda_{t+1},
+            # u_t and u_{t-1} and writes lambda_{t-1}, 2*S bytes per point update;
+            # "effective" prices every update at the one-step 3*S
             forms[f"adjoint_{name}"] = {"glups": round(glups(ms_a, Ta), 3), "ms_per_step": round(ms_a / Ta, 4),
-                                        "hbm_frac": round(frac(ms_a, 3 * S, Ta), 4)}
+                                        "effective_hbm_frac": round(frac(ms_a, 3 * S, Ta), 4),
+                                        "hbm_frac_per_launch": round(frac(ms_a, 2 * S, Ta), 4)}
             # the same steps also accumulating the sum of the adjoint inputs
             # (dL/df, dL/dgamma): one more read and write of a field per pass
             log(f"timing adjoint kernel {name} with dL/df and dL/dgamma")
@@ -583,7 +662,10 @@ def main():
     # --------------------------------------------------------- CPU oracle
     if not args.no_cpu_baseline:
         log("timing the CPU oracle (bounded sample) ...")
-        out["cpu_baseline"] = cpu_baseline(u0_h, f_h, coeffs, bc)
+        out["cpu_baseline"], ref64 = cpu_baseline(u0_h, f_h, coeffs, bc)
+        if not args.no_errors:
+            log("errors of the GPU forms against the oracle ...")
+            out["errors"] = form_errors(dev, u0, f64, u0_h, f_h, coeffs, bc, ref64)
     print(json.dumps(out), flush=True)
 
 
