@@ -152,12 +152,16 @@ int dcp_step_unfused(int dtype, const void *u, const void *f, void *u_out,
  *   u     [N]   in: u_0; out: u_T
  *   f     [N]   in (must not overlap u)
  *   T           >= 0 (T = 0 leaves u unchanged)
- *   tblock      steps fused per pass over memory (temporal blocking), 1 or 2;
- *               1 = one pass per step.  Values > 1 need impl = DCP_FUSED.
- *               A two-step pass is used where the grid allows it (x-rows
- *               that fit the LDS budget, 16-byte aligned fields); the other
- *               steps run one per pass.  Either way every point is computed
- *               with the same operations, so u_T is bitwise the same.
+ *   tblock      most steps fused per pass over memory (temporal blocking),
+ *               1, 2 or 3; 1 = one pass per step.  Values > 1 need impl =
+ *               DCP_FUSED and 16-byte aligned fields with nx a multiple of
+ *               the 16-byte vector (2 doubles, 4 floats).  Passes of tblock
+ *               steps run on tiles of whole x-rows, or of x-segments with a
+ *               halo of recomputed points when rows are too long for a
+ *               whole-row tile; T mod tblock remaining steps run as shorter
+ *               passes (dcp_run_plan reports the passes).  Either way every
+ *               point is computed with the same operations, so u_T is
+ *               bitwise the same for every tblock.
  *   energy [T]  out, optional: energy[t-1] = sum u_t^2, t = 1..T (double)
  *   resid  [T]  out, optional: resid[t-1] = sqrt(sum (u_t - u_{t-1})^2)
  *   ckpt        out, optional: ceil(T/k) consecutive fields; slot c holds
@@ -171,6 +175,25 @@ int dcp_run(int dtype, int impl, void *u, const void *f, int64_t nx,
             int32_t T, int32_t tblock, double *energy, double *resid,
             void *ckpt, int32_t ckpt_every, void *ws, size_t ws_bytes,
             void *stream);
+
+/*
+ * How a dcp_run with these arguments takes its steps, for 16-byte aligned
+ * fields (what torch and hipMalloc return): passes over memory of one, two
+ * and three steps, so that a caller can see when a grid falls back to
+ * shorter passes.  Host only; asks the current device for its LDS size when
+ * there is one.  Writes *info (a host pointer); argument errors as dcp_run.
+ */
+typedef struct {
+    int32_t passes[3];      /* passes of 1, 2 and 3 steps                      */
+    int32_t steps_per_pass; /* the most steps any pass takes (0: no steps)     */
+    int32_t segmented;      /* multi-step passes over x-segments with a halo
+                               (1) or over whole rows (0)                      */
+    int32_t tile_rows;      /* rows per tile of the multi-step passes          */
+    int32_t lanes;          /* lanes per workgroup of the multi-step passes    */
+} dcp_run_info;
+
+int dcp_run_plan(int dtype, int impl, int64_t nx, int64_t ny, int64_t nz,
+                 int32_t T, int32_t tblock, int norms, dcp_run_info *info);
 
 /*
  * Reverse-mode gradient through T fused steps, from the checkpoints that

@@ -36,6 +36,12 @@ class Coeffs(ctypes.Structure):
         return dict(alpha=self.alpha, beta=self.beta, gamma=self.gamma, h=self.h, dt=self.dt)
 
 
+class RunInfo(ctypes.Structure):
+    """dcp_run_info: the passes a dcp_run takes."""
+    _fields_ = [("passes", ctypes.c_int32 * 3), ("steps_per_pass", ctypes.c_int32),
+                ("segmented", ctypes.c_int32), ("tile_rows", ctypes.c_int32), ("lanes", ctypes.c_int32)]
+
+
 class DcpError(RuntimeError):
     def __init__(self, fn: str, status: int, msg: str):
         super().__init__(f"{fn} failed: {msg} (status {status})")
@@ -69,6 +75,8 @@ def lib() -> ctypes.CDLL:
     L.dcp_run.argtypes = [c_int, c_int, vp, vp, i64, i64, i64, cp, c_int, i32, i32, dp, dp, vp, i32,
                           vp, sz, vp]
     L.dcp_run.restype = c_int
+    L.dcp_run_plan.argtypes = [c_int, c_int, i64, i64, i64, i32, i32, c_int, ctypes.POINTER(RunInfo)]
+    L.dcp_run_plan.restype = c_int
     L.dcp_adjoint_run.argtypes = [c_int, vp, i32, vp, vp, i64, i64, i64, cp, c_int, i32, i32, vp, dp,
                                   vp, dp, vp, sz, vp]
     L.dcp_adjoint_run.restype = c_int
@@ -111,6 +119,18 @@ def workspace_bytes(op: int, dtype: int, nx: int, ny: int, nz: int, T: int = 0,
           lib().dcp_workspace_bytes(op, dtype, impl, nx, ny, nz, T, ckpt_every, tblock,
                                     int(bool(norms)), ctypes.byref(out)))
     return out.value
+
+
+def run_plan(dtype: int, nx: int, ny: int, nz: int, T: int, tblock: int, norms: bool = True,
+             impl: int = FUSED) -> dict:
+    """The passes dcp_run takes for these arguments (16-byte aligned fields):
+    {'passes': [one-step, two-step, three-step], 'steps_per_pass',
+    'segmented', 'tile_rows', 'lanes'}."""
+    info = RunInfo()
+    check("dcp_run_plan", lib().dcp_run_plan(dtype, impl, nx, ny, nz, T, tblock, int(bool(norms)),
+                                             ctypes.byref(info)))
+    return {"passes": list(info.passes), "steps_per_pass": info.steps_per_pass, "segmented": info.segmented,
+            "tile_rows": info.tile_rows, "lanes": info.lanes}
 
 
 def jacobi_workspace_bytes(dims: int, n0: int, n1: int, tsteps: int, tblock: int = 0) -> int:

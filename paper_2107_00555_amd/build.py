@@ -33,7 +33,7 @@ COMMON = [
     f"-I{INCLUDE}", f"-I{CSRC}",
 ]
 
-SOURCES = ["dcp_kernels.hip", "dcp_tblock.hip", "dcp_jacobi.hip", "dcp_api.cpp", "dcp_revolve.cpp",
+SOURCES = ["dcp_kernels.hip", "dcp_tblock.hip", "dcp_tbk.hip", "dcp_jacobi.hip", "dcp_api.cpp", "dcp_revolve.cpp",
            "dcp_fuse.cpp"]
 
 

@@ -3,6 +3,7 @@
 // loop and of the checkpointed adjoint.  All device work is enqueued on the
 // caller's stream; nothing here synchronises or allocates device memory.
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <initializer_list>
@@ -151,6 +152,24 @@ struct RunWs {
 // LDS of one workgroup on gfx950, the most a two-step pass may plan for.
 constexpr size_t kLdsMax = 160 * 1024;
 
+// Plan of a B-step pass (dcp_tbk.hip).  DCP_TBK_CFG="wc,ty,lanes" restricts
+// the planner to segments of wc chunks (a value covering the row: whole
+// rows), slabs of ty rows and 1024 or 512 lanes; 0 leaves a choice to the
+// planner.  A tuning override only: every choice computes the same states
+// bit for bit (the norms' summation order follows the tiles).
+bool tbk_for(int dtype, const Geo &g, int B, bool vok, size_t lds_limit, TbkTile *t) {
+    int wc = 0, ty = 0, lanes = 1024;
+    if (const char *e = std::getenv("DCP_TBK_CFG")) {
+        int a = 0, b = 0, c = 0;
+        if (std::sscanf(e, "%d,%d,%d", &a, &b, &c) == 3) {
+            wc = a > 0 ? a : 0;
+            ty = b > 0 ? b : 0;
+            lanes = c == 512 ? 512 : 1024;
+        }
+    }
+    return tbk_plan(dtype, B, g.nx, g.ny, g.nz, vok, lds_limit, lanes, wc, ty, t);
+}
+
 int layout_run(int dtype, int impl, const Geo &g, int32_t T, int32_t tblock, bool norms, RunWs *w) {
     size_t off = 0;
     if (g.n == 0 || T == 0) {
@@ -170,6 +189,10 @@ int layout_run(int dtype, int impl, const Geo &g, int32_t T, int32_t tblock, boo
         if (impl == DCP_FUSED && tblock >= 2 && tb_plan(dtype, g.nx, g.ny, g.nz, true, kLdsMax, &tb) &&
             tb.nblk > nb)
             nb = tb.nblk;
+        for (int B = 2; impl == DCP_FUSED && B <= tblock && B <= 3; ++B) {
+            TbkTile tk;
+            if (tbk_for(dtype, g, B, true, kLdsMax, &tk) && tk.nblk > nb) nb = tk.nblk;
+        }
         w->nblk = nb;
         w->partials = off;
         off += align_up((size_t)T * nb * 2 * sizeof(double));
@@ -319,14 +342,77 @@ hipError_t tb_fwd_pass(int dtype, int bc, const Geo &g, const dcp_coeffs &c, con
     return launch_tb2(dtype, SOP_FWD, bc, part1 != nullptr, tb, ta, st);
 }
 
+// LDS one workgroup may use on the current device (gfx950's 160 KiB when no
+// device can be asked, for plans made on a host without one).
+size_t device_lds() {
+    int dev = 0, lds = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || lds <= 0)
+        return kLdsMax;
+    return (size_t)lds;
+}
+
 // Plans a two-step pass when asked for and supported by the grid and device.
 bool plan_tb(int dtype, const Geo &g, int32_t tblock, bool vok, TbTile *tb) {
     if (tblock < 2) return false;
-    int dev = 0, lds = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
-        return false;
-    return tb_plan(dtype, g.nx, g.ny, g.nz, vok, (size_t)lds, tb);
+    return tb_plan(dtype, g.nx, g.ny, g.nz, vok, device_lds(), tb);
+}
+
+// Plans a B-step pass (B = 2, 3) when the grid and the device allow it.
+bool plan_tbk(int dtype, const Geo &g, int B, bool vok, TbkTile *t) {
+    return tbk_for(dtype, g, B, vok, device_lds(), t);
+}
+
+// The passes of a fused dcp_run: three steps where tblock >= 3 and the
+// B-step kernel applies; two steps over whole rows where the two-step kernel
+// applies, else over x-segments; one step otherwise and for the remainders.
+// stride: partial-sum slots per step of the run's workspace (norms only).
+struct PassPlan {
+    bool use_tb = false, use_k2 = false, use_k3 = false;
+    TbTile tb{};
+    TbkTile k2{}, k3{};
+    int32_t len_at(int32_t s, int32_t T) const {
+        if (use_k3 && s + 3 <= T) return 3;
+        if ((use_tb || use_k2) && s + 2 <= T) return 2;
+        return 1;
+    }
+};
+
+PassPlan plan_passes(int dtype, int impl, const Geo &g, int32_t T, int32_t tblock, bool vok, bool norms,
+                     int stride) {
+    PassPlan pp;
+    if (impl != DCP_FUSED) return pp;
+    pp.use_tb = T >= 2 && plan_tb(dtype, g, tblock, vok, &pp.tb) && (!norms || pp.tb.nblk <= stride);
+    pp.use_k2 = !pp.use_tb && T >= 2 && tblock >= 2 && plan_tbk(dtype, g, 2, vok, &pp.k2) &&
+                (!norms || pp.k2.nblk <= stride);
+    pp.use_k3 = T >= 3 && tblock >= 3 && plan_tbk(dtype, g, 3, vok, &pp.k3) && (!norms || pp.k3.nblk <= stride);
+    return pp;
+}
+
+// A B-step pass u_t -> u_{t+B}; mid[s-1] receives u_{t+s} when not null;
+// part (when not null) holds the B steps' partial-sum arrays.
+hipError_t tbk_fwd_pass(int dtype, int bc, const Geo &g, const dcp_coeffs &c, const TbkTile &tk, const void *u,
+                        const void *f, void *out, void *const mid[2], double *const part[3], hipStream_t st) {
+    TbkArgs a{};
+    a.u = u;
+    a.f = f;
+    a.out = out;
+    for (int i = 0; i < 2; ++i) a.mid[i] = mid ? mid[i] : nullptr;
+    for (int i = 0; i < 3; ++i) a.part[i] = part ? part[i] : nullptr;
+    a.nx = g.nx;
+    a.ny = g.ny;
+    a.nz = g.nz;
+    a.c0 = c.dt * c.alpha / (c.h * c.h);
+    a.c1 = c.dt * c.beta;
+    a.c2 = c.dt * c.gamma;
+    a.ty = tk.ty;
+    a.nslab = tk.nslab;
+    a.nseg = tk.nseg;
+    a.zc = tk.zc;
+    a.wc = tk.wc;
+    a.halo = tk.halo;
+    a.chf = tk.chf;
+    return launch_tbk(dtype, bc, part != nullptr, tk, a, st);
 }
 
 bool vec_ok_for(int dtype, const Geo &g, std::initializer_list<const void *> ptrs) {
@@ -484,7 +570,7 @@ const char *dcp_status_string(int status) {
     }
 }
 
-int32_t dcp_max_tblock(int dtype) { return (dtype == DCP_F64 || dtype == DCP_F32) ? 2 : 1; }
+int32_t dcp_max_tblock(int dtype) { return (dtype == DCP_F64 || dtype == DCP_F32) ? 3 : 1; }
 
 int dcp_workspace_bytes(int op, int dtype, int impl, int64_t nx, int64_t ny, int64_t nz, int32_t T,
                         int32_t ckpt_every, int32_t tblock, int norms, size_t *bytes) {
@@ -582,10 +668,13 @@ int dcp_run(int dtype, int impl, void *u, const void *f, int64_t nx, int64_t ny,
     const int stride = w.nblk;  // partial slots per step (>= every kernel's workgroup count)
     double *partials = norms ? reinterpret_cast<double *>(at(ws, w.partials)) : nullptr;
 
-    // two-step passes where the grid allows them and the device has the LDS
-    TbTile tb{};
-    const bool use_tb = impl == DCP_FUSED && T >= 2 && plan_tb(dtype, g, tblock, vok, &tb) &&
-                        (!norms || tb.nblk <= stride);
+    // passes of several steps where the grid allows them and the device has
+    // the LDS: three steps (tblock 3), two steps over whole rows (tblock >= 2,
+    // rows that fit the LDS) or over x-segments (longer rows)
+    const PassPlan pp = plan_passes(dtype, impl, g, T, tblock, vok, norms, stride);
+    const bool use_tb = pp.use_tb;
+    const TbTile &tb = pp.tb;
+    const TbkTile &tk2 = pp.k2, &tk3 = pp.k3;
 
     // workgroup count behind each step's partials, for the fixed-order finalize
     std::vector<int> step_nblk;
@@ -595,11 +684,20 @@ int dcp_run(int dtype, int impl, void *u, const void *f, int64_t nx, int64_t ny,
     if (nslots > 0) DCP_TRY(launch_ew(dtype, EW_COPY, u, nullptr, slot(0), 0.0, g.n, vok, st));
     const void *cur = u;
     for (int32_t s = 0; s < T;) {
-        const int32_t len = (use_tb && s + 2 <= T) ? 2 : 1;
+        const int32_t len = pp.len_at(s, T);
         const int32_t se = s + len;
         void *nxt = is_ckpt(se) ? slot(se / ckpt_every) : ((cur == u) ? buf : u);
         double *p = partials ? partials + (size_t)s * stride * 2 : nullptr;
-        if (len == 2) {
+        if (len == 3 || (len == 2 && !use_tb)) {
+            // checkpoints at the middle steps are stored by the pass itself
+            const TbkTile &tk = len == 3 ? tk3 : tk2;
+            void *mid[2] = {is_ckpt(s + 1) ? slot((s + 1) / ckpt_every) : nullptr,
+                            len == 3 && is_ckpt(s + 2) ? slot((s + 2) / ckpt_every) : nullptr};
+            double *part[3] = {p, p ? p + (size_t)stride * 2 : nullptr, p ? p + (size_t)stride * 4 : nullptr};
+            DCP_TRY(tbk_fwd_pass(dtype, bc, g, *coeffs, tk, cur, f, nxt, mid, p ? part : nullptr, st));
+            if (norms)
+                for (int32_t i = s; i < se; ++i) step_nblk[i] = tk.nblk;
+        } else if (len == 2) {
             // a checkpoint at the middle step is stored by the pass itself
             void *mid = is_ckpt(s + 1) ? slot((s + 1) / ckpt_every) : nullptr;
             DCP_TRY(tb_fwd_pass(dtype, bc, g, *coeffs, tb, cur, f, nxt, mid, p,
@@ -623,6 +721,39 @@ int dcp_run(int dtype, int impl, void *u, const void *f, int64_t nx, int64_t ny,
                                     energy ? energy + s0 : nullptr, resid ? resid + s0 : nullptr, 1, st));
             s0 = s1;
         }
+    }
+    return DCP_OK;
+}
+
+int dcp_run_plan(int dtype, int impl, int64_t nx, int64_t ny, int64_t nz, int32_t T, int32_t tblock, int norms,
+                 dcp_run_info *info) {
+    if (!info) return DCP_E_NULL;
+    Geo g;
+    int rc = check_geo(dtype, nx, ny, nz, &g);
+    if (rc) return rc;
+    if (impl != DCP_FUSED && impl != DCP_UNFUSED) return DCP_E_ARG;
+    if (T < 0 || tblock < 1 || tblock > dcp_max_tblock(dtype)) return DCP_E_ARG;
+    if (tblock > 1 && impl != DCP_FUSED) return DCP_E_ARG;
+    RunWs w;
+    if ((rc = layout_run(dtype, impl, g, T, tblock, norms != 0, &w))) return rc;
+    std::memset(info, 0, sizeof(*info));
+    if (T == 0 || g.n == 0) return DCP_OK;
+    const int wide = dtype == DCP_F64 ? 2 : 4;
+    const PassPlan pp = plan_passes(dtype, impl, g, T, tblock, g.nx % wide == 0, norms != 0, w.nblk);
+    int32_t most = 0;
+    for (int32_t s = 0; s < T;) {
+        const int32_t len = pp.len_at(s, T);
+        ++info->passes[len - 1];
+        most = len > most ? len : most;
+        s += len;
+    }
+    info->steps_per_pass = most;
+    if (most >= 2) {
+        const bool k = most == 3 || !pp.use_tb;
+        const TbkTile &tk = most == 3 ? pp.k3 : pp.k2;
+        info->segmented = k && tk.seg ? 1 : 0;
+        info->tile_rows = k ? tk.ty : pp.tb.ty;
+        info->lanes = k ? tk.nt : 1024;
     }
     return DCP_OK;
 }

@@ -104,6 +104,36 @@ bool tb_plan(int dtype, int64_t nx, int64_t ny, int64_t nz, bool vec_ok, size_t 
 hipError_t launch_tb2(int dtype, int op, int bc, bool reduce, const TbTile &t, const TbArgs &a,
                       hipStream_t stream);
 
+// B fused forward steps per pass (B = 2 or 3) on tiles of full rows or of
+// x-segments with a halo (dcp_tbk.hip).
+//   u = u_t, f = f, out = u_{t+B}; mid[s-1] = u_{t+s} (s = 1 .. B-1) on the
+//   owned points, or null; part[s-1] = norms of step t+s ([nblk][2]) when
+//   the pass reduces.
+struct TbkArgs {
+    const void *u;
+    const void *f;
+    void *out;
+    void *mid[2];
+    double *part[3];
+    int64_t nx, ny, nz;
+    double c0, c1, c2;
+    int ty, nslab, nseg, zc, wc, halo, chf;
+};
+struct TbkTile {
+    int B, vec, ty, nt, km;
+    bool seg;             // x-segments with a halo (false: whole rows)
+    int wc, halo, chf;    // segment chunks, halo chunks per side, frame chunks per row
+    int nseg, nslab, zc, nruns, nblk;
+    size_t lds_bytes;
+};
+// Plans a B-step pass; false if the kernel does not apply (no 16-byte lanes,
+// or no tile fits the LDS).  lanes: 1024 or 512 lanes per workgroup.  When
+// force_wc > 0 only segments of that many chunks (or whole rows, if it
+// covers the row) are considered; force_ty > 0 fixes the slab height.
+bool tbk_plan(int dtype, int B, int64_t nx, int64_t ny, int64_t nz, bool vec_ok, size_t lds_limit, int lanes,
+              int force_wc, int force_ty, TbkTile *t);
+hipError_t launch_tbk(int dtype, int bc, bool reduce, const TbkTile &t, const TbkArgs &a, hipStream_t stream);
+
 // Fixed-order reduction of [nsteps][stride][2] partials (first nblk used).
 //   mode 0: out0[0] = sum k=0, out0[1] = sum k=1          (one step)
 //   mode 1: out0[s] = sum k=0, out1[s] = sqrt(sum k=1)   (either may be null)

@@ -170,7 +170,7 @@ def test_adjoint_argument_errors(L, host_only):
     assert adj_call(L, ws=F) == -7
     assert adj_call(L, c=coeffs(L, beta=float("-inf"))) == -5
     assert adj_call(L, tb=0) == -5
-    assert adj_call(L, tb=3) == -5
+    assert adj_call(L, tb=4) == -5
     assert adj_call(L, gf=F) == -7              # grad_f aliases f
     assert adj_call(L, gf=O + 8) == -7          # grad_f overlaps grad_u0
     assert adj_call(L, gf=WS + 64) == -7        # grad_f inside the workspace
@@ -289,7 +289,7 @@ def rev_adj(L, dtype=0, f=F, lam=U, n=(8, 8, 8), bc=0, T=5, s=2, tb=1, g=O, gab=
 def test_revolve_argument_errors(L, host_only):
     assert rev_fwd(L, T=-1) == -5
     assert rev_fwd(L, s=-1) == -5
-    assert rev_fwd(L, tb=3) == -5
+    assert rev_fwd(L, tb=4) == -5
     assert rev_fwd(L, u=None) == -1
     assert rev_fwd(L, f=U) == -7
     assert rev_fwd(L, ws=U + 64) == -7
@@ -304,3 +304,30 @@ def test_revolve_argument_errors(L, host_only):
     assert rev_adj(L, gf=O) == -7
     assert rev_adj(L, gf=0x68000000, gg=0x60000008) == -7
     assert rev_adj(L, wsb=64) == -6
+
+
+def test_run_plan_reports_the_passes(L, monkeypatch):
+    # which passes dcp_run takes (host-side plan; 160 KiB of LDS without a GPU)
+    monkeypatch.delenv("DCP_TBK_CFG", raising=False)
+    p = L.run_plan(L.F64, 512, 512, 512, 100, 3)
+    assert p["passes"] == [1, 0, 33] and p["steps_per_pass"] == 3
+    p = L.run_plan(L.F64, 512, 512, 512, 100, 2)
+    assert p["passes"] == [0, 50, 0] and p["steps_per_pass"] == 2 and p["segmented"] == 0
+    p = L.run_plan(L.F32, 512, 512, 512, 100, 3)
+    assert p["passes"] == [1, 0, 33]
+    p = L.run_plan(L.F64, 512, 512, 512, 100, 1)
+    assert p["passes"] == [100, 0, 0] and p["steps_per_pass"] == 1
+    p = L.run_plan(L.F64, 512, 512, 512, 7, 1, impl=L.UNFUSED)
+    assert p["passes"] == [7, 0, 0]
+    # rows too long for a whole-row tile: two-step passes over x-segments
+    for dtype, nx in ((L.F64, 1024), (L.F64, 1030), (L.F32, 2048)):
+        p = L.run_plan(dtype, nx, 1024, 512, 200, 2)
+        assert p["passes"] == [0, 100, 0] and p["segmented"] == 1, (dtype, nx, p)
+    # rows that are not a whole number of 16-byte vectors: one step per pass
+    p = L.run_plan(L.F64, 513, 16, 16, 10, 3)
+    assert p["passes"] == [10, 0, 0]
+    assert L.run_plan(L.F64, 0, 16, 16, 10, 3)["passes"] == [0, 0, 0]
+    with pytest.raises(L.DcpError):
+        L.run_plan(L.F64, 8, 8, 8, 10, 4)
+    with pytest.raises(L.DcpError):
+        L.run_plan(L.F64, 8, 8, 8, 10, 2, impl=L.UNFUSED)
