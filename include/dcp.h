@@ -56,6 +56,14 @@
  *
  * Empty grids (nx, ny or nz equal to 0) are valid: fields are untouched and
  * every requested norm or gradient sum is written as 0.
+ *
+ * Tuning.  The tile and pass choices are the library's own.  For tuning
+ * runs only, the environment variables DCP_TILE_SHAPE, DCP_TILE_ZC,
+ * DCP_TB_CFG, DCP_TBK_CFG, DCP_FUSE_ZR, DCP_J1_K, DCP_J2_CFG and DCP_J2_MODE
+ * force a tiling or schedule; they are read at each call and honoured only
+ * while DCP_TUNING=1 is set as well.  A forced choice computes the same
+ * fields bit for bit; the double norms and sums may differ in rounding (their
+ * summation order follows the tiles).
  */
 #ifndef DCP_H
 #define DCP_H
@@ -197,7 +205,12 @@ int dcp_run_plan(int dtype, int impl, int64_t nx, int64_t ny, int64_t nz,
 
 /*
  * Reverse-mode gradient through T fused steps, from the checkpoints that
- * dcp_run wrote.  With J_t = I + dt*alpha*L - diag(3*beta*dt*u_t^2):
+ * dcp_run wrote.  The paper defines no adjoint: these formulas are the
+ * chain rule applied to the step's statement (J_t is the Jacobian of one
+ * step with respect to u_t; the parameter sums differentiate the same
+ * statement with respect to alpha, beta, gamma and f), and the checkpointed
+ * recomputation is the standard every-k scheme.
+ * With J_t = I + dt*alpha*L - diag(3*beta*dt*u_t^2):
  *     lambda_T = lam_T
  *     lambda_t = J_t^T lambda_{t+1}                    (t = T-1 .. 0)
  *     dL/dalpha = sum_t dt * <lambda_{t+1}, L u_t>

@@ -64,7 +64,7 @@ bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
 
 // ------------------------------------------------------------- tile choice
 int env_int(const char *name, int def) {
-    const char *s = std::getenv(name);
+    const char *s = tuning_env(name);
     if (!s || !*s) return def;
     return std::atoi(s);
 }
@@ -89,7 +89,8 @@ Tile make_tile(const Geo &g, int vec, int shape, int zc) {
 }
 
 // Tile for one field operand layout.  The default is tuned for the 512^3
-// class of grids; DCP_TILE_SHAPE / DCP_TILE_ZC override it for tuning runs.
+// class of grids; DCP_TILE_SHAPE / DCP_TILE_ZC override it in tuning runs
+// (with DCP_TUNING=1).
 Tile pick_tile(int dtype, const Geo &g, bool vec_ok) {
     const int wide = dtype == DCP_F64 ? 2 : 4;
     const int vec = vec_ok ? wide : 1;
@@ -159,7 +160,7 @@ constexpr size_t kLdsMax = 160 * 1024;
 // bit for bit (the norms' summation order follows the tiles).
 bool tbk_for(int dtype, const Geo &g, int B, bool vok, size_t lds_limit, TbkTile *t) {
     int wc = 0, ty = 0, lanes = 1024;
-    if (const char *e = std::getenv("DCP_TBK_CFG")) {
+    if (const char *e = tuning_env("DCP_TBK_CFG")) {
         int a = 0, b = 0, c = 0;
         if (std::sscanf(e, "%d,%d,%d", &a, &b, &c) == 3) {
             wc = a > 0 ? a : 0;

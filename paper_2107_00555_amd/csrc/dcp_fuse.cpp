@@ -46,6 +46,7 @@
 #include <vector>
 
 #include "dcp.h"
+#include "dcp_internal.h"
 
 namespace {
 
@@ -871,7 +872,7 @@ int dcp_fuse_run(dcp_fused *p, const void *const *inputs, const double *params, 
     int64_t tiles_x = (nx + tile_w - 1) / tile_w;
     int64_t zr = 1;
     while (zr < 16 && tiles_x * ny * ((nz + 2 * zr - 1) / (2 * zr)) >= 4 * 4096) zr *= 2;
-    if (const char *e = std::getenv("DCP_FUSE_ZR")) {  // tuning override: planes per wave tile
+    if (const char *e = dcp::tuning_env("DCP_FUSE_ZR")) {  // tuning override: planes per wave tile
         const long v = std::strtol(e, nullptr, 10);
         if (v >= 1 && v <= 4096) zr = v;
     }

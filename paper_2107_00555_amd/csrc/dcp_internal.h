@@ -5,10 +5,24 @@
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
 
 #include <vector>
 
 namespace dcp {
+
+// Tuning overrides: environment variables that force a tiling or a pass
+// schedule (DCP_TILE_SHAPE, DCP_TILE_ZC, DCP_TB_CFG, DCP_TBK_CFG,
+// DCP_FUSE_ZR, DCP_J1_K, DCP_J2_CFG, DCP_J2_MODE).  They are honoured only
+// while DCP_TUNING=1 is also set, so a stray variable alone changes nothing.
+// Every forced choice computes the same fields; a norm's summation order
+// follows the tiles.
+inline const char *tuning_env(const char *name) {
+    const char *on = getenv("DCP_TUNING");
+    if (!on || strcmp(on, "1") != 0) return nullptr;
+    return getenv(name);
+}
 
 enum StencilOp : int {
     SOP_FWD = 0,  // u' = u + c0*(S6 - 6u) - c1*u^3 + c2*f      (S6 = sum of 6 neighbours)

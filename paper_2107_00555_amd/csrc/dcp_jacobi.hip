@@ -28,6 +28,7 @@
 #include <type_traits>
 
 #include "dcp.h"
+#include "dcp_internal.h"
 
 namespace {
 
@@ -417,7 +418,7 @@ constexpr size_t kJAlign = 256;
 // work over more CUs.  DCP_J1_K forces a length (tuning runs only).
 int j1_pick_k(int64_t n, int64_t hh) {
     auto admissible = [&](int k) { return 64 * k - 2 * hh >= 32 * k; };
-    const char *forced = std::getenv("DCP_J1_K");
+    const char *forced = dcp::tuning_env("DCP_J1_K");
     if (forced && *forced) {
         const int k = std::atoi(forced);
         if ((k == 4 || k == 8 || k == 16 || k == 32) && 64 * k > 2 * hh) return k;
@@ -467,12 +468,12 @@ J2Plan j2_pick(int64_t n0, int64_t n1, int64_t hh) {
     int64_t all = 0;
     const int64_t in = j2_interior_tiles(n0, n1, hh, kJ2Cfgs[0].w * kJ2Cfgs[0].rpl, &all);
     if (all >= 2048 && in * 10 >= all * 9) p = J2Plan{0, true};
-    const char *fc = std::getenv("DCP_J2_CFG");
+    const char *fc = dcp::tuning_env("DCP_J2_CFG");
     if (fc && *fc) {
         const int c = std::atoi(fc);
         if (c >= 0 && c < 3 && kJ2Cfgs[c].w * kJ2Cfgs[c].rpl > 2 * hh) p.cfg = c;
     }
-    const char *fm = std::getenv("DCP_J2_MODE");
+    const char *fm = dcp::tuning_env("DCP_J2_MODE");
     if (fm && *fm) p.split = std::atoi(fm) == 2;
     return p;
 }

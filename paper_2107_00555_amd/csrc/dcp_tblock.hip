@@ -502,7 +502,7 @@ bool tb_plan(int dtype, int64_t nx, int64_t ny, int64_t nz, bool vec_ok, size_t 
     if (!vec_ok || nx <= 0 || ny <= 0 || nz <= 0 || nx % vec != 0) return false;
     if (nx > (1 << 24) || nx * ny > (int64_t)INT32_MAX || nz > (1 << 29) || ny > (1 << 29)) return false;
     const int64_t ch = nx / vec;
-    const char *forced = std::getenv("DCP_TB_CFG");  // tuning runs only
+    const char *forced = tuning_env("DCP_TB_CFG");  // tuning runs only
     const int only = (forced && *forced) ? std::atoi(forced) : -1;
     for (int i = 0; i < kNumTbCfgs; ++i) {
         if (only >= 0 && i != only) continue;
@@ -544,7 +544,7 @@ hipError_t launch_tb2(int dtype, int op, int bc, bool reduce, const TbTile &t, c
     // without scratch; measured 7% faster at 512^3 in FP64 and FP32.  The
     // adjoint keeps 512 lanes: its 1024-lane build spills under periodic
     // boundaries and measured no faster (FP64) or slower (FP32).
-    const char *forced = std::getenv("DCP_TB_CFG");  // tuning runs only
+    const char *forced = tuning_env("DCP_TB_CFG");  // tuning runs only
     if (op == SOP_FWD && n512 && !(forced && *forced) && t.lds_bytes >= (size_t)(1024 / 64) * 4 * sizeof(double))
         n1024 = true;
     if (dtype == 0) {

@@ -54,11 +54,15 @@ class Expr:
 
 def lap7(u: Expr, h=None) -> Expr:
     """(u[x-1] + u[x+1] + u[y-1] + u[y+1] + u[z-1] + u[z+1] - 6u) / h^2,
-    added left to right; without h, the sum times no factor."""
+    added left to right; without h, the sum times no factor.  h^2 is a
+    statement of the program (a scalar product of two literals, rounded in
+    the program's dtype like every other operation)."""
     s = u.shift(-1, 0, 0) + u.shift(1, 0, 0) + u.shift(0, -1, 0) + u.shift(0, 1, 0) \
         + u.shift(0, 0, -1) + u.shift(0, 0, 1)
     d = s - 6.0 * u
-    return d if h is None else d / (h * h)
+    if h is None:
+        return d
+    return d / u.p._stmt("mul", float(h), float(h))
 
 
 class Program:

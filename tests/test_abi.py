@@ -331,3 +331,17 @@ def test_run_plan_reports_the_passes(L, monkeypatch):
         L.run_plan(L.F64, 8, 8, 8, 10, 4)
     with pytest.raises(L.DcpError):
         L.run_plan(L.F64, 8, 8, 8, 10, 2, impl=L.UNFUSED)
+
+
+def test_tuning_overrides_need_the_master_switch(L, monkeypatch):
+    # a tiling variable alone changes nothing; with DCP_TUNING=1 it is honoured
+    monkeypatch.delenv("DCP_TUNING", raising=False)
+    monkeypatch.delenv("DCP_TBK_CFG", raising=False)
+    default = L.run_plan(L.F64, 512, 512, 512, 100, 3)
+    monkeypatch.setenv("DCP_TBK_CFG", "32,4,512")
+    assert L.run_plan(L.F64, 512, 512, 512, 100, 3) == default
+    monkeypatch.setenv("DCP_TUNING", "1")
+    forced = L.run_plan(L.F64, 512, 512, 512, 100, 3)
+    assert forced["segmented"] == 1 and forced["tile_rows"] == 4 and forced["lanes"] == 512, forced
+    monkeypatch.setenv("DCP_TUNING", "0")
+    assert L.run_plan(L.F64, 512, 512, 512, 100, 3) == default

@@ -71,6 +71,7 @@ def test_jacobi_2d_matches_oracle_bitwise(shape, tsteps, tblock):
 def test_jacobi_1d_every_run_length(monkeypatch, k, n, tsteps, tblock):
     """Each compiled points-per-lane variant, forced through the tuning knob
     (the library ignores it when the halo does not fit)."""
+    monkeypatch.setenv("DCP_TUNING", "1")
     monkeypatch.setenv("DCP_J1_K", str(k))
     A, B = inputs.jacobi_fields(1, n, seed=k + n)
     say(f"jacobi_1d K={k} n={n} tsteps={tsteps} tblock={tblock}")
@@ -86,6 +87,7 @@ def test_jacobi_2d_every_workgroup_shape(monkeypatch, mode, cfg, shape, tsteps, 
     """Each compiled workgroup shape and both launch modes (one masked launch
     over all tiles; the ring of edge tiles masked plus the interior tiles
     unmasked), forced through the tuning knobs."""
+    monkeypatch.setenv("DCP_TUNING", "1")
     monkeypatch.setenv("DCP_J2_CFG", str(cfg))
     monkeypatch.setenv("DCP_J2_MODE", str(mode))
     A, B = inputs.jacobi_fields(2, shape[0], seed=cfg + shape[0], n1=shape[1])
@@ -110,6 +112,7 @@ def oracle_2d_paper():
 
 @pytest.mark.parametrize("tblock,cfg", [(0, ""), (1, ""), (16, ""), (12, "1"), (12, "2")])
 def test_jacobi_2d_paper_size_full_run(monkeypatch, oracle_2d_paper, tblock, cfg):
+    monkeypatch.setenv("DCP_TUNING", "1")
     monkeypatch.setenv("DCP_J2_CFG", cfg)
     A, B, want = oracle_2d_paper
     T = inputs.JACOBI_WORKLOADS["jacobi_2d_paper"]["tsteps"]

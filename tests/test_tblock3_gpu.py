@@ -108,6 +108,7 @@ FORCED = [(wc, ty, lanes) for wc in (1 << 20, 32, 64, 128, 256) for ty in (4, 8,
 def test_every_tiling_gives_the_same_states(monkeypatch, wc, ty, lanes):
     from paper_2107_00555_amd import _lib
     say("forced tiling", wc, ty, lanes)
+    monkeypatch.setenv("DCP_TUNING", "1")
     monkeypatch.setenv("DCP_TBK_CFG", f"{wc},{ty},{lanes}")
     used = 0
     for shape in ((600, 37, 11), (96, 37, 11)):
