@@ -86,6 +86,8 @@ typedef enum {
                              unknown impl or op                               */
     DCP_E_WORKSPACE = -6, /* ws_bytes smaller than dcp_workspace_bytes(...)    */
     DCP_E_ALIAS = -7,     /* an output overlaps an input it must not overlap   */
+    DCP_E_SCRATCH = -8,   /* the call needs more than the fixed device scratch
+                             of dcp_step_fused_noalloc                        */
     DCP_E_HIP = -100      /* a HIP launch or copy failed                       */
 } dcp_status;
 
@@ -137,6 +139,29 @@ int dcp_step_fused(int dtype, const void *u, const void *f, void *u_out,
                    int64_t nx, int64_t ny, int64_t nz, const dcp_coeffs *coeffs,
                    int bc, double *norms2, void *ws, size_t ws_bytes,
                    void *stream);
+
+/*
+ * dcp_step_fused without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and rules as
+ * dcp_step_fused, minus ws and ws_bytes: the per-workgroup partial sums of
+ * norms2 live in a fixed device array of DCP_NOALLOC_SCRATCH_BYTES (1 MiB)
+ * that the library holds on every GPU it runs on until the process ends.
+ * The call allocates nothing.  It uses the scratch of the current device,
+ * so u, f, u_out, norms2 and stream must belong to that device.
+ * The scratch is needed only when norms2 is requested (16 bytes per
+ * workgroup of the one-step tiling, which covers grids of more than 10^9
+ * points); a grid that needs more returns DCP_E_SCRATCH before anything is
+ * enqueued.  Calls that overlap in time on one GPU (on different streams,
+ * or from different threads) share the scratch and race: serialise them.
+ * A call overwrites every scratch entry it reads, so nothing carries over
+ * from an earlier call.
+ */
+#define DCP_NOALLOC_SCRATCH_BYTES ((size_t)1 << 20)
+int dcp_step_fused_noalloc(int dtype, const void *u, const void *f, void *u_out,
+                           int64_t nx, int64_t ny, int64_t nz,
+                           const dcp_coeffs *coeffs, int bc, double *norms2,
+                           void *stream);
 
 /*
  * The same step as the unfused single-operator program of Sec. 2.3, one

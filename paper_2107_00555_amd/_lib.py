@@ -17,6 +17,8 @@ F64, F32 = 0, 1
 DIRICHLET0, PERIODIC = 0, 1
 FUSED, UNFUSED = 0, 1
 OP_STEP_FUSED, OP_STEP_UNFUSED, OP_RUN, OP_ADJOINT = 0, 1, 2, 3
+E_SCRATCH = -8
+NOALLOC_SCRATCH_BYTES = 1 << 20  # DCP_NOALLOC_SCRATCH_BYTES
 
 
 class Coeffs(ctypes.Structure):
@@ -72,6 +74,8 @@ def lib() -> ctypes.CDLL:
     L.dcp_step_fused.restype = c_int
     L.dcp_step_unfused.argtypes = step_args
     L.dcp_step_unfused.restype = c_int
+    L.dcp_step_fused_noalloc.argtypes = [c_int, vp, vp, vp, i64, i64, i64, cp, c_int, dp, vp]
+    L.dcp_step_fused_noalloc.restype = c_int
     L.dcp_run.argtypes = [c_int, c_int, vp, vp, i64, i64, i64, cp, c_int, i32, i32, dp, dp, vp, i32,
                           vp, sz, vp]
     L.dcp_run.restype = c_int

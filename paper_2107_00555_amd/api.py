@@ -16,7 +16,7 @@ from ._lib import (DIRICHLET0, F32, F64, FUSED, OP_ADJOINT, OP_RUN, OP_STEP_FUSE
                    OP_STEP_UNFUSED, PERIODIC, UNFUSED, Coeffs, DcpError)
 
 __all__ = ["Coeffs", "DcpError", "DIRICHLET0", "PERIODIC", "FUSED", "UNFUSED",
-           "step", "run", "adjoint_run", "workspace", "num_slots", "bc_code", "impl_code",
+           "step", "step_noalloc", "run", "adjoint_run", "workspace", "num_slots", "bc_code", "impl_code",
            "jacobi_1d", "jacobi_2d", "revolve_forward", "revolve_adjoint"]
 
 
@@ -127,6 +127,29 @@ def step(u: torch.Tensor, f: torch.Tensor, coeffs, bc, impl="fused", norms: bool
         _lib.check(fn.__name__, fn(dt, _ptr(u), _ptr(f), _ptr(out), nx, ny, nz, ctypes.byref(c),
                                    bc_code(bc), _ptr(n2), _ptr(ws), wsb, _stream(u.device)))
     return out, n2
+
+
+def step_noalloc(u: torch.Tensor, f: torch.Tensor, coeffs, bc, out: torch.Tensor,
+                 norms2: torch.Tensor | None = None) -> None:
+    """One fused step u -> out through dcp_step_fused_noalloc: the caller
+    passes every buffer (out, and norms2 as a float64 tensor of 2 elements
+    when the norms are wanted) and neither this function nor the library
+    allocates device memory; the norms' partial sums use the library's
+    fixed per-GPU scratch (calls overlapping on one GPU race)."""
+    u = _field("u", u)
+    f = _field("f", f, u)
+    _field("out", out, u)
+    if norms2 is not None:
+        if (not isinstance(norms2, torch.Tensor) or norms2.dtype != torch.float64 or norms2.numel() != 2
+                or norms2.device != u.device or not norms2.is_contiguous()):
+            raise ValueError("norms2 must be a contiguous float64 tensor of 2 elements on u's device")
+    dt = _dtype_code(u)
+    nz, ny, nx = u.shape
+    c = Coeffs.make(coeffs)
+    with torch.cuda.device(u.device):
+        _lib.check("dcp_step_fused_noalloc", _lib.lib().dcp_step_fused_noalloc(
+            dt, _ptr(u), _ptr(f), _ptr(out), nx, ny, nz, ctypes.byref(c), bc_code(bc), _ptr(norms2),
+            _stream(u.device)))
 
 
 def run(u: torch.Tensor, f: torch.Tensor, coeffs, T: int, bc, impl="fused", tblock: int | None = None,

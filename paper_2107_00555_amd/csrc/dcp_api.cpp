@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <initializer_list>
+#include <mutex>
 #include <vector>
 
 #include "dcp.h"
@@ -566,6 +567,8 @@ const char *dcp_status_string(int status) {
         case DCP_E_ARG: return "invalid argument (T, ckpt_every, tblock, h, impl, op or a non-finite coefficient)";
         case DCP_E_WORKSPACE: return "workspace too small";
         case DCP_E_ALIAS: return "an output overlaps an input";
+        case DCP_E_SCRATCH:
+            return "the grid needs more than the 1 MiB device scratch of the allocation-free entry point";
         case DCP_E_HIP: return "HIP launch or copy failed";
         default: return "unknown status";
     }
@@ -611,6 +614,57 @@ int dcp_workspace_bytes(int op, int dtype, int impl, int64_t nx, int64_t ny, int
 int dcp_step_fused(int dtype, const void *u, const void *f, void *u_out, int64_t nx, int64_t ny, int64_t nz,
                    const dcp_coeffs *coeffs, int bc, double *norms2, void *ws, size_t ws_bytes, void *stream) {
     return step_common(DCP_FUSED, dtype, u, f, u_out, nx, ny, nz, coeffs, bc, norms2, ws, ws_bytes, stream);
+}
+
+// ------------------------------------------------ allocation-free fused step
+// Scratch of dcp_step_fused_noalloc: the norms' per-workgroup partial sums.
+// Every GPU holds its own copy (with the code object) until the process
+// ends.  In host code `scratch` names a host-side stand-in, never the device
+// memory: kernels and copies get the address hipGetSymbolAddress returns for
+// the current device, fetched once per device.
+static __device__ __align__(256) double scratch[DCP_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_of_current_device(void **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return DCP_E_HIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return DCP_E_HIP;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return DCP_OK;
+}
+
+}  // namespace
+
+int dcp_step_fused_noalloc(int dtype, const void *u, const void *f, void *u_out, int64_t nx, int64_t ny,
+                           int64_t nz, const dcp_coeffs *coeffs, int bc, double *norms2, void *stream) {
+    // argument errors first (the same checks as dcp_step_fused), then the size
+    Geo g;
+    int rc = check_geo(dtype, nx, ny, nz, &g);
+    if (rc) return rc;
+    if (bc != DCP_DIRICHLET0 && bc != DCP_PERIODIC) return DCP_E_BC;
+    if ((rc = check_coeffs(coeffs))) return rc;
+    if (g.n > 0 && (!u || !f || !u_out)) return DCP_E_NULL;
+    StepWs w;
+    if ((rc = layout_step(dtype, DCP_FUSED, g, norms2 != nullptr, &w))) return rc;
+    if (w.total > DCP_NOALLOC_SCRATCH_BYTES) return DCP_E_SCRATCH;
+    const size_t fb = g.bytes();
+    if (overlaps(u_out, fb, u, fb) || overlaps(u_out, fb, f, fb)) return DCP_E_ALIAS;
+    if (norms2 && (overlaps(norms2, 16, u, fb) || overlaps(norms2, 16, f, fb) || overlaps(norms2, 16, u_out, fb)))
+        return DCP_E_ALIAS;
+    void *ws = nullptr;
+    if (w.total > 0 && (rc = scratch_of_current_device(&ws))) return rc;
+    return step_common(DCP_FUSED, dtype, u, f, u_out, nx, ny, nz, coeffs, bc, norms2, ws,
+                       w.total > 0 ? (size_t)DCP_NOALLOC_SCRATCH_BYTES : 0, stream);
 }
 
 int dcp_step_unfused(int dtype, const void *u, const void *f, void *u_out, int64_t nx, int64_t ny, int64_t nz,
