@@ -44,11 +44,14 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 # multiplies issue at the same instruction rate and count one flop each.
 FP64_NONFMA_PEAK_TFLOPS = 78.6 / 2
 KERNEL_SRCS = {1: os.path.join(ROOT, "paper_2107_00555_amd", "csrc", "dcp_kernels.hip"),
-               2: os.path.join(ROOT, "paper_2107_00555_amd", "csrc", "dcp_tblock.hip")}
+               2: os.path.join(ROOT, "paper_2107_00555_amd", "csrc", "dcp_tblock.hip"),
+               3: os.path.join(ROOT, "paper_2107_00555_amd", "csrc", "dcp_tbk.hip")}
 COUNTERS = {1: os.path.join(ROOT, "profiles", "stencil_fused_f64_512_counters.md"),
-            2: os.path.join(ROOT, "profiles", "tb2_fused_f64_512_counters.md")}
+            2: os.path.join(ROOT, "profiles", "tb2_fused_f64_512_counters.md"),
+            3: os.path.join(ROOT, "profiles", "tbk3_fused_f64_512_counters.md")}
 KERNEL_NAMES = {1: "stencil_kernel<double,2,1,4,4,PERIODIC,FWD,norms> (one step per launch)",
-                2: "tb2_kernel<double,2,4,1024,2,PERIODIC,FWD,norms> (two steps per launch)"}
+                2: "tb2_kernel<double,2,4,1024,2,PERIODIC,FWD,norms> (two steps per launch)",
+                3: "tbk_kernel<double,2,3,1024,2,PERIODIC,segments,norms> (three steps per launch)"}
 
 
 def parse():
@@ -69,8 +72,8 @@ def parse():
                    help="skip the one-half-step-per-pass comparison runs of the Jacobi forms")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="also run a plain 1 GiB device copy (counter calibration)")
-    p.add_argument("--tblock", type=int, default=2,
-                   help="time steps fused per pass over memory in the headline run (1 or 2)")
+    p.add_argument("--tblock", type=int, default=3,
+                   help="time steps fused per pass over memory in the headline run (1, 2 or 3)")
     return p.parse_args()
 
 
@@ -200,8 +203,8 @@ def form_errors(dev, u0, f64, u0_h, f_h, coeffs, bc, ref64) -> dict:
                 "resid_max_rel": float(np.max(np.abs(r - r_or) / r_or))}
 
     errs = {"steps": T, "reference": "oracle (FP64, serial) after the same steps from u0"}
-    for name, impl, tb in (("fused_f64_tblock2", "fused", 2), ("fused_f64_tblock1", "fused", 1),
-                           ("unfused_f64", "unfused", 1)):
+    for name, impl, tb in (("fused_f64_tblock3", "fused", 3), ("fused_f64_tblock2", "fused", 2),
+                           ("fused_f64_tblock1", "fused", 1), ("unfused_f64", "unfused", 1)):
         u = u0.clone()
         out = api.run(u, f64, coeffs, T, bc, impl=impl, tblock=tb, norms=True)
         torch.cuda.synchronize()
@@ -214,7 +217,7 @@ def form_errors(dev, u0, f64, u0_h, f_h, coeffs, bc, ref64) -> dict:
     f32h = f_h.astype(np.float32).astype(np.float64)
     ref32 = oracle.run(u32h, f32h, coeffs, T, bc, norms=True)
     f32 = f64.to(torch.float32)
-    for tb in (2, 1):
+    for tb in (3, 2, 1):
         u = u0.to(torch.float32)
         out = api.run(u, f32, coeffs, T, bc, impl="fused", tblock=tb, norms=True)
         torch.cuda.synchronize()
@@ -427,7 +430,7 @@ def main():
 
     # ---------------------------------------------------------- headline
     ws = api.workspace(_lib.workspace_bytes(_lib.OP_RUN, _lib.F64, nx, ny, nz, T=T, norms=True,
-                                            tblock=2), dev)
+                                            tblock=3), dev)
     res = {}
 
     def fused_step():
@@ -441,14 +444,27 @@ def main():
         torch.cuda.synchronize()
         del uc
 
-    if args.tblock not in (1, 2):
-        raise SystemExit("--tblock must be 1 or 2")
-    log(f"timing fused f64: T={T}, tblock={args.tblock}, K={args.steps}, W={args.warmup}")
+    if args.tblock not in (1, 2, 3):
+        raise SystemExit("--tblock must be 1, 2 or 3")
+    plan = _lib.run_plan(_lib.F64, nx, ny, nz, T, args.tblock)
+    log(f"timing fused f64: T={T}, tblock={args.tblock}, K={args.steps}, W={args.warmup}, passes {plan['passes']}")
     total_ms, per, wall = timed(fused_step, args.steps, args.warmup, stream)
     ms_step = total_ms / args.steps
     value = N * T * args.steps / (total_ms / 1e3) / 1e9
-    launches = T // args.tblock                     # kernel launches per benchmark step
-    launch_ms = total_ms / (args.steps * launches)  # average launch (includes the tiny finalize)
+    # launches of the dominant kernel per benchmark step (passes of tblock
+    # steps); the remainder passes of fewer steps (T mod tblock) are timed on
+    # their own below and taken out, so the average is that kernel's alone
+    B = plan["steps_per_pass"]
+    launches = plan["passes"][B - 1]
+    rest = [(n_, L_ + 1) for L_, n_ in enumerate(plan["passes"]) if L_ + 1 != B and n_]
+    rest_ms = 0.0
+    for n_, L_ in rest:
+        ur = u0.clone()
+        ms_r, _, _ = timed(lambda: api.run(ur, f64, coeffs, L_, bc, impl="fused", tblock=args.tblock,
+                                           norms=True, ws=ws), args.steps, 1, stream)
+        rest_ms += n_ * ms_r / args.steps
+        del ur
+    launch_ms = (ms_step - rest_ms) / launches     # includes the tiny finalize of the norms
     bytes_per_launch = 3 * 8 * N                    # read u, read f, write the result (algorithmic)
     achieved = bytes_per_launch / (launch_ms / 1e3) / 1e9
     med, lo, hi = bootstrap_ci(per)
@@ -472,15 +488,18 @@ def main():
         "data": "synthetic (seeded: u0 ~ U[-1,1], f = 8 low-frequency sinusoids)",
         "config": {"workload": "fwd_512_f64: 512^3 float64, periodic, fused forward, T=100 steps "
                                "per step of the benchmark, FP64 energy+residual norms every step, "
-                               f"{args.tblock} time step(s) per pass over memory",
+                               f"up to {args.tblock} time step(s) per pass over memory",
                    "grid": [nx, ny, nz], "T": T, "bc": "periodic", "impl": "fused",
-                   "tblock": args.tblock, "coeffs": coeffs, "parallelism": "single-gpu"},
+                   "tblock": args.tblock, "passes": plan["passes"], "coeffs": coeffs,
+                   "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     "kernel": KERNEL_NAMES[args.tblock],
+                     "kernel": KERNEL_NAMES[B],
                      "bytes_per_launch": bytes_per_launch,
                      "avg_launch_ms": round(launch_ms, 5),
+                     "launches_per_step": launches,
+                     "other_passes_ms_per_step": round(rest_ms, 4),
                      # lattice updates x the one-step algorithmic 24 B, over the peak:
                      # above 1 once a launch fuses more than one time step
                      "effective_frac": round(value * 24 / HBM_PEAK_GBS, 4)},
@@ -493,23 +512,34 @@ def main():
         out["forms"] = forms
         kk = max(1, min(args.steps, 3))
 
-        def glups(ms, steps=T):
-            return N * steps / (ms / 1e3) / 1e9
+        def glups(ms, steps=T, n=N):
+            return n * steps / (ms / 1e3) / 1e9
 
-        def frac(ms, bpl, steps=T):
-            return (bpl * N * steps / (ms / 1e3) / 1e9) / HBM_PEAK_GBS
+        def frac(ms, bpl, steps=T, n=N):
+            return (bpl * n * steps / (ms / 1e3) / 1e9) / HBM_PEAK_GBS
 
-        forms[f"fused_f64_tblock{args.tblock}"] = {"glups": round(value, 3), "ms": round(ms_step, 3),
-                                                   "effective_hbm_frac": round(frac(ms_step, 24), 4)}
-        other = 3 - args.tblock
-        uo = u0.clone()
-        log(f"timing fused f64 tblock={other}")
-        ms_o, _, _ = timed(lambda: api.run(uo, f64, coeffs, T, bc, impl="fused", tblock=other, norms=True, ws=ws),
-                           args.steps, 1, stream)
-        ms_o /= args.steps
-        forms[f"fused_f64_tblock{other}"] = {"glups": round(glups(ms_o), 3), "ms": round(ms_o, 3),
-                                             "effective_hbm_frac": round(frac(ms_o, 24), 4)}
-        del uo
+        def fused_entry(ms, S, tb, shape=(nx, ny, nz), steps=T):
+            # effective: every update priced at the one-step 3*S bytes;
+            # per pass: the algorithmic 3*S bytes of each pass over memory
+            code = _lib.F64 if S == 8 else _lib.F32
+            pl = _lib.run_plan(code, *shape, steps, tb)
+            n = shape[0] * shape[1] * shape[2]
+            return {"glups": round(glups(ms, steps, n), 3), "ms": round(ms, 3), "passes": pl["passes"],
+                    "segmented": pl["segmented"], "effective_hbm_frac": round(frac(ms, 3 * S, steps, n), 4),
+                    "hbm_frac_per_pass": round(frac(ms, 3 * S * sum(pl["passes"]) / steps, steps, n), 4)}
+
+        ms_f = {args.tblock: ms_step}
+        for tb in (1, 2, 3):
+            if tb == args.tblock:
+                continue
+            uo = u0.clone()
+            log(f"timing fused f64 tblock={tb}")
+            ms_o, _, _ = timed(lambda: api.run(uo, f64, coeffs, T, bc, impl="fused", tblock=tb, norms=True,
+                                               ws=ws), args.steps, 1, stream)
+            ms_f[tb] = ms_o / args.steps
+            del uo
+        for tb in (1, 2, 3):
+            forms[f"fused_f64_tblock{tb}"] = fused_entry(ms_f[tb], 8, tb)
 
         # unfused chain, float64
         wsu = api.workspace(_lib.workspace_bytes(_lib.OP_RUN, _lib.F64, nx, ny, nz, T=T, norms=True,
@@ -522,9 +552,7 @@ def main():
         forms["unfused_f64"] = {"glups": round(glups(ms_u), 3), "ms": round(ms_u, 3),
                                 "bytes_per_lup": 21 * 8 + 16,
                                 "hbm_frac": round(frac(ms_u, 21 * 8 + 16), 4)}
-        ms_f = {args.tblock: ms_step, other: ms_o}
-        forms["fused_speedup_over_unfused_f64"] = {"tblock1": round(ms_u / ms_f[1], 3),
-                                                   "tblock2": round(ms_u / ms_f[2], 3)}
+        forms["fused_speedup_over_unfused_f64"] = {f"tblock{tb}": round(ms_u / ms_f[tb], 3) for tb in (1, 2, 3)}
         del wsu, uu
 
         # float32 forms
@@ -533,15 +561,14 @@ def main():
         ws32 = api.workspace(max(_lib.workspace_bytes(_lib.OP_RUN, _lib.F32, nx, ny, nz, T=T, norms=True,
                                                       impl=_lib.UNFUSED),
                                  _lib.workspace_bytes(_lib.OP_RUN, _lib.F32, nx, ny, nz, T=T, norms=True,
-                                                      tblock=2)), dev)
+                                                      tblock=3)), dev)
         ms32 = {}
-        for tb in (1, 2):
+        for tb in (1, 2, 3):
             log(f"timing fused f32 tblock={tb}")
             ms_f32, _, _ = timed(lambda: api.run(u32, f32, coeffs, T, bc, impl="fused", tblock=tb, norms=True,
                                                  ws=ws32), args.steps, 1, stream)
             ms32[tb] = ms_f32 / args.steps
-            forms[f"fused_f32_tblock{tb}"] = {"glups": round(glups(ms32[tb]), 3), "ms": round(ms32[tb], 3),
-                                              "effective_hbm_frac": round(frac(ms32[tb], 12), 4)}
+            forms[f"fused_f32_tblock{tb}"] = fused_entry(ms32[tb], 4, tb)
         u32b = u0.to(torch.float32)
         log("timing unfused f32")
         ms_u32, _, _ = timed(lambda: api.run(u32b, f32, coeffs, T, bc, impl="unfused", norms=True, ws=ws32),
@@ -549,9 +576,37 @@ def main():
         ms_u32 /= kk
         forms["unfused_f32"] = {"glups": round(glups(ms_u32), 3), "ms": round(ms_u32, 3),
                                 "hbm_frac": round(frac(ms_u32, 21 * 4 + 8), 4)}
-        forms["fused_speedup_over_unfused_f32"] = {"tblock1": round(ms_u32 / ms32[1], 3),
-                                                   "tblock2": round(ms_u32 / ms32[2], 3)}
+        forms["fused_speedup_over_unfused_f32"] = {f"tblock{tb}": round(ms_u32 / ms32[tb], 3) for tb in (1, 2, 3)}
         del ws32, u32b
+
+        # rows longer than a whole-row tile holds in LDS: 1024 x 1024 x 512
+        # (multi-step passes over x-segments), both dtypes, 24 steps
+        wshape = (1024, 1024, 512)
+        Tw = 24
+        for dname, tdt, S, code in (("f64", torch.float64, 8, _lib.F64), ("f32", torch.float32, 4, _lib.F32)):
+            gw = torch.Generator(device=dev)
+            gw.manual_seed(args.seed + 11)
+            uw0 = torch.empty((wshape[2], wshape[1], wshape[0]), dtype=tdt, device=dev).uniform_(-1, 1, generator=gw)
+            fw = torch.empty_like(uw0).uniform_(-1, 1, generator=gw)
+            uw = uw0.clone()
+            wsw = api.workspace(_lib.workspace_bytes(_lib.OP_RUN, code, *wshape, T=Tw, norms=True, tblock=3), dev)
+            ref = None
+            for tb in (1, 2, 3):
+                log(f"timing wide rows {wshape} {dname} tblock={tb}")
+                uw.copy_(uw0)
+                api.run(uw, fw, coeffs, Tw, bc, impl="fused", tblock=tb, norms=True, ws=wsw)
+                torch.cuda.synchronize()
+                if ref is None:
+                    ref = uw.clone()
+                elif not torch.equal(ref, uw):
+                    raise RuntimeError(f"wide-row passes of {tb} steps differ from one-step passes")
+                ms_w, _, _ = timed(lambda: api.run(uw, fw, coeffs, Tw, bc, impl="fused", tblock=tb, norms=True,
+                                                   ws=wsw), kk, 1, stream)
+                ent = fused_entry(ms_w / kk, S, tb, shape=wshape, steps=Tw)
+                ent["T"] = Tw
+                forms[f"wide_1024x1024x512_{dname}_tblock{tb}"] = ent
+            del uw0, fw, uw, wsw, ref
+            torch.cuda.empty_cache()
 
         # adjoint kernel alone: k = 1 (no recomputation), 10 steps
         for name, dtype, fld, ff in (("f64", torch.float64, u0, f64), ("f32", torch.float32, u32, f32)):
@@ -614,10 +669,67 @@ def main():
                                                      "ms_over_forward": round(ms_ga / ms_step, 3)}
         del ck, wsf, wsa
 
+        # the two gradient workloads as stated: 256^3 float64 ghost-zero,
+        # T=50, a checkpoint every 10 steps; 1024x1024x512 float32 periodic,
+        # T=200, every 20 steps.  Loss 0.5*||u_T - u_tgt||^2, so the adjoint
+        # starts from u_T - u_tgt.  One benchmark step: the forward run with
+        # checkpoints, then the checkpointed adjoint (recomputation included).
+        GiB = float(1 << 30)
+        for wname in ("grad_256_f64", "grad_large_f32"):
+            w = inputs.WORKLOADS[wname]
+            gx, gy, gz = w["shape"]
+            Tg, kg, bcg = w["T"], w["ckpt_every"], w["bc"]
+            tdt = torch.float64 if w["dtype"] == "f64" else torch.float32
+            code = _lib.F64 if w["dtype"] == "f64" else _lib.F32
+            log(f"timing gradient workload {wname}: inputs ...")
+            gu0_h, gf_h = inputs.make_fields(wname, seed=args.seed)
+            gu0 = torch.from_numpy(gu0_h).to(dev, tdt)
+            gf = torch.from_numpy(gf_h).to(dev, tdt)
+            del gu0_h, gf_h
+            gtgt = torch.from_numpy(inputs.target(gx, gy, gz, seed=args.seed)).to(dev, tdt)
+            gN = gx * gy * gz
+            gu = gu0.clone()
+            gck = torch.empty((api.num_slots(Tg, kg), gz, gy, gx), dtype=tdt, device=dev)
+            gwsf = api.workspace(_lib.workspace_bytes(_lib.OP_RUN, code, gx, gy, gz, T=Tg, tblock=3), dev)
+            gwsa = api.workspace(_lib.workspace_bytes(_lib.OP_ADJOINT, code, gx, gy, gz, T=Tg, ckpt_every=kg,
+                                                      tblock=2), dev)
+            gg = torch.empty_like(gu0)
+            glam = torch.empty_like(gu0)
+
+            def fwd_only():
+                gu.copy_(gu0)
+                api.run(gu, gf, coeffs, Tg, bcg, tblock=3, norms=False, ckpt_every=kg, ws=gwsf, ckpt=gck)
+
+            def adj_only():
+                api.adjoint_run(gck, kg, gf, glam, coeffs, Tg, bcg, ws=gwsa, grad_u0=gg)
+
+            def full():
+                fwd_only()
+                torch.sub(gu, gtgt, out=glam)
+                adj_only()
+
+            log(f"timing gradient workload {wname}")
+            ms_full, _, _ = timed(full, kk, 1, stream)
+            ms_fwd, _, _ = timed(fwd_only, kk, 1, stream)
+            full()
+            ms_adj, _, _ = timed(adj_only, kk, 1, stream)
+            ms_full, ms_fwd, ms_adj = ms_full / kk, ms_fwd / kk, ms_adj / kk
+            S = 8 if tdt == torch.float64 else 4
+            mem = (gck.numel() * S + (gwsf.numel() if gwsf is not None else 0) + gwsa.numel()
+                   + 5 * gN * S)  # u0, u, f, u_tgt (lam), dL/du0
+            forms[f"gradient_{wname}"] = {
+                "grid": [gx, gy, gz], "dtype": w["dtype"], "bc": "periodic" if bcg == inputs.PERIODIC else "dirichlet0",
+                "T": Tg, "ckpt_every": kg, "ms": round(ms_full, 3),
+                "forward_with_checkpoints_ms": round(ms_fwd, 3),
+                "adjoint_ms": round(ms_adj, 3),
+                "adjoint_glups_incl_recompute": round(glups(ms_adj, Tg, gN), 3),
+                "device_memory_gib": round(mem / GiB, 2)}
+            del gu0, gf, gtgt, gu, gck, gwsf, gwsa, gg, glam
+            torch.cuda.empty_cache()
+
         # memory-bounded gradient over T=1000 steps: binomial checkpointing
         # with 8 snapshots against a checkpoint every 32 steps
         Tr, slots, kr = 1000, 8, 32
-        GiB = float(1 << 30)
         log(f"timing gradient f64 T={Tr}: binomial checkpointing with {slots} snapshots")
 
         def rev_grad():

@@ -24,8 +24,9 @@
 //   * workgroups are numbered so that the tiles one XCD runs at a time are
 //     neighbours in space (the hardware deals workgroups round-robin to the
 //     8 XCDs, each with its own L2), so halo rows hit in that XCD's L2.
-// Reductions (norms, gradient sums) are accumulated per lane in double,
-// combined by a fixed butterfly within the wave and a fixed order across
+// Reductions (norms, gradient sums) are accumulated per lane in double
+// (each term added with one fused multiply-add), combined by a fixed
+// butterfly within the wave and a fixed order across
 // waves, and written as one pair per workgroup; a second kernel adds the
 // per-workgroup pairs in a fixed order.  Results are therefore identical
 // from run to run (the tiled write-conflict reduction of Sec. 3.1, made
@@ -66,6 +67,35 @@ __device__ __forceinline__ void store_vec(T *p, const T (&s)[VEC]) {
 #pragma unroll
         for (int i = 0; i < VEC; ++i) v[i] = s[i];
         *reinterpret_cast<V *>(p) = v;
+    }
+}
+
+// Non-temporal forms, for data that each launch reads or writes once (the
+// point operand, the result, element-wise operands): the loads and stores
+// carry the streaming hint, so they do not displace the stencil operand's
+// rows, which neighbouring tiles read again through L2.
+template <typename T, int VEC>
+__device__ __forceinline__ void load_vec_nt(T (&d)[VEC], const T *p) {
+    if constexpr (VEC == 1) {
+        d[0] = __builtin_nontemporal_load(p);
+    } else {
+        typedef typename VecT<T, VEC>::type V;
+        V v = __builtin_nontemporal_load(reinterpret_cast<const V *>(p));
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) d[i] = v[i];
+    }
+}
+
+template <typename T, int VEC>
+__device__ __forceinline__ void store_vec_nt(T *p, const T (&s)[VEC]) {
+    if constexpr (VEC == 1) {
+        __builtin_nontemporal_store(s[0], p);
+    } else {
+        typedef typename VecT<T, VEC>::type V;
+        V v;
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) v[i] = s[i];
+        __builtin_nontemporal_store(v, reinterpret_cast<V *>(p));
     }
 }
 
@@ -143,7 +173,7 @@ __global__ void __launch_bounds__(64 * BXW * BY) stencil_kernel(StencilArgs a) {
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             if (active && r < nrow)
-                load_vec<T, VEC>(d[r], Q + z * sz + (yf + r) * sy + x0);
+                load_vec_nt<T, VEC>(d[r], Q + z * sz + (yf + r) * sy + x0);
             else
                 zero_vec<T, VEC>(d[r]);
         }
@@ -227,9 +257,9 @@ __global__ void __launch_bounds__(64 * BXW * BY) stencil_kernel(StencilArgs a) {
                                 res[e] = acc;
                                 if constexpr (RED) {
                                     const double d = (double)acc;
-                                    acc0 += d * d;
+                                    acc0 = fma(d, d, acc0);
                                     const double dd = d - (double)c;
-                                    acc1 += dd * dd;
+                                    acc1 = fma(dd, dd, acc1);
                                 }
                             } else {  // SOP_ADJ: c = lambda_{t+1}, qv = u_t
                                 T acc = fma(C0, lapn, c);
@@ -237,22 +267,22 @@ __global__ void __launch_bounds__(64 * BXW * BY) stencil_kernel(StencilArgs a) {
                                 res[e] = acc;
                                 if constexpr (RED) {
                                     const double du = (double)qv;
-                                    acc0 += (double)lapn * du;
-                                    acc1 += (double)c * (du * du * du);
+                                    acc0 = fma((double)lapn, du, acc0);
+                                    acc1 = fma((double)c, du * du * du, acc1);
                                 }
                             }
                         }
                     }
-                    store_vec<T, VEC>(O + z * sz + (yf + r) * sy + x0, res);
+                    store_vec_nt<T, VEC>(O + z * sz + (yf + r) * sy + x0, res);
                     if constexpr (OP == SOP_ADJL) {
                         // running sum of the adjoint inputs: lam += lambda_{t+1}
                         T *lp = static_cast<T *>(a.lam) + z * sz + (yf + r) * sy + x0;
                         T lv[VEC];
                         if (a.lam_first) zero_vec<T, VEC>(lv);
-                        else load_vec<T, VEC>(lv, lp);
+                        else load_vec_nt<T, VEC>(lv, lp);
 #pragma unroll
                         for (int e = 0; e < VEC; ++e) lv[e] = lv[e] + uc[r][e];
-                        store_vec<T, VEC>(lp, lv);
+                        store_vec_nt<T, VEC>(lp, lv);
                     }
                 }
             }
@@ -397,9 +427,9 @@ __global__ void __launch_bounds__(256)
         for (int u = 0; u < U; ++u) {
             const int64_t i = j + u * 256;
             if (i < end) {
-                if constexpr (OPC != EW_ZERO) load_vec<T, VEC>(xv[u], x + i * VEC);
+                if constexpr (OPC != EW_ZERO) load_vec_nt<T, VEC>(xv[u], x + i * VEC);
                 else zero_vec<T, VEC>(xv[u]);
-                if constexpr (BIN) load_vec<T, VEC>(yv[u], y + i * VEC);
+                if constexpr (BIN) load_vec_nt<T, VEC>(yv[u], y + i * VEC);
                 else zero_vec<T, VEC>(yv[u]);
             }
         }
@@ -408,7 +438,7 @@ __global__ void __launch_bounds__(256)
             const int64_t i = j + u * 256;
             if (i < end) {
                 ew_apply<T, VEC, OPC>(ov[u], xv[u], yv[u], a);
-                store_vec<T, VEC>(o + i * VEC, ov[u]);
+                store_vec_nt<T, VEC>(o + i * VEC, ov[u]);
             }
         }
     }
@@ -461,8 +491,8 @@ __global__ void __launch_bounds__(256)
     };
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nv; i += stride) {
         T ov[VEC], uv[VEC];
-        load_vec<T, VEC>(ov, o + i * VEC);
-        load_vec<T, VEC>(uv, u + i * VEC);
+        load_vec_nt<T, VEC>(ov, o + i * VEC);
+        load_vec_nt<T, VEC>(uv, u + i * VEC);
 #pragma unroll
         for (int e = 0; e < VEC; ++e) term(ov[e], uv[e]);
     }

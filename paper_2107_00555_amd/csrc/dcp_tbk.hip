@@ -56,6 +56,26 @@ __device__ __forceinline__ void k_store(T *p, const T (&s)[VEC]) {
     *reinterpret_cast<V *>(p) = v;
 }
 
+// Streaming (non-temporal) forms for data a pass touches once: f and the
+// stored states.  u_t keeps ordinary loads: the neighbouring tiles read its
+// halo rows and chunks again through L2.
+template <typename T, int VEC>
+__device__ __forceinline__ void k_load_nt(T (&d)[VEC], const T *p) {
+    typedef typename KVec<T, VEC>::type V;
+    V v = __builtin_nontemporal_load(reinterpret_cast<const V *>(p));
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) d[i] = v[i];
+}
+
+template <typename T, int VEC>
+__device__ __forceinline__ void k_store_nt(T *p, const T (&s)[VEC]) {
+    typedef typename KVec<T, VEC>::type V;
+    V v;
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) v[i] = s[i];
+    __builtin_nontemporal_store(v, reinterpret_cast<V *>(p));
+}
+
 template <typename T, int VEC>
 __device__ __forceinline__ void k_zero(T (&d)[VEC]) {
 #pragma unroll
@@ -202,7 +222,7 @@ __global__ void __launch_bounds__(NT) tbk_kernel(TbkArgs a) {
 #pragma unroll
         for (int k = 0; k < KM; ++k) {
             if ((flags[k] & 2u) && gofs[k] >= 0 && zr >= 0)
-                k_load<T, VEC>(d[k], F + (int64_t)zr * sz + gofs[k]);
+                k_load_nt<T, VEC>(d[k], F + (int64_t)zr * sz + gofs[k]);
             else
                 k_zero<T, VEC>(d[k]);
         }
@@ -304,18 +324,18 @@ __global__ void __launch_bounds__(NT) tbk_kernel(TbkArgs a) {
                 const bool here = (fl & kOwned) && owned_plane;
                 if (s < B) {
                     k_store<T, VEC>(dst + o, res);
-                    if (mid && here) k_store<T, VEC>(mid + (int64_t)p * sz + gofs[k], res);
+                    if (mid && here) k_store_nt<T, VEC>(mid + (int64_t)p * sz + gofs[k], res);
                 } else if (fl & kOwned) {
-                    k_store<T, VEC>(O + (int64_t)p * sz + gofs[k], res);
+                    k_store_nt<T, VEC>(O + (int64_t)p * sz + gofs[k], res);
                 }
                 if constexpr (RED) {
                     if (here) {
 #pragma unroll
                         for (int e = 0; e < VEC; ++e) {
                             const double d = (double)res[e];
-                            es[s - 1] += d * d;
+                            es[s - 1] = fma(d, d, es[s - 1]);
                             const double dd = d - (double)c[e];
-                            rs[s - 1] += dd * dd;
+                            rs[s - 1] = fma(dd, dd, rs[s - 1]);
                         }
                     }
                 }

@@ -65,6 +65,35 @@ __device__ __forceinline__ void tb_store(T *p, const T (&s)[VEC]) {
     }
 }
 
+// Streaming (non-temporal) forms for data a pass touches once: the point
+// operands, the stored states and the running sum.  The stencil operand
+// keeps ordinary loads: neighbouring slabs read its halo rows again
+// through L2.
+template <typename T, int VEC>
+__device__ __forceinline__ void tb_load_nt(T (&d)[VEC], const T *p) {
+    if constexpr (VEC == 1) {
+        d[0] = __builtin_nontemporal_load(p);
+    } else {
+        typedef typename TbVec<T, VEC>::type V;
+        V v = __builtin_nontemporal_load(reinterpret_cast<const V *>(p));
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) d[i] = v[i];
+    }
+}
+
+template <typename T, int VEC>
+__device__ __forceinline__ void tb_store_nt(T *p, const T (&s)[VEC]) {
+    if constexpr (VEC == 1) {
+        __builtin_nontemporal_store(s[0], p);
+    } else {
+        typedef typename TbVec<T, VEC>::type V;
+        V v;
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) v[i] = s[i];
+        __builtin_nontemporal_store(v, reinterpret_cast<V *>(p));
+    }
+}
+
 template <typename T, int VEC>
 __device__ __forceinline__ void tb_zero(T (&d)[VEC]) {
 #pragma unroll
@@ -112,7 +141,8 @@ __device__ __forceinline__ int tb_xcd_remap(int b, int nb) {
 // one-step kernel: s6 = ((xm + xp) + (ym + yp)) + (zm + zp).
 //   forward: u + c0*(s6 - 6u) - c1*u^3 + c2*f        (c1 = dt*beta)
 //   adjoint: l + c0*(s6 - 6l) - c1*u^2*l             (c1 = 3*dt*beta), with the
-//            parameter sums (s6 - 6l)*u and l*u^3 in double
+//            parameter sums (s6 - 6l)*u and l*u^3 accumulated in double by
+//            fused multiply-adds when `add` is set
 template <typename T>
 __device__ __forceinline__ T tb_fwd(T c, T xm, T xp, T ym, T yp, T zm, T zp, T fq, T C0, T C1, T C2) {
     const T s6 = ((xm + xp) + (ym + yp)) + (zm + zp);
@@ -124,15 +154,17 @@ __device__ __forceinline__ T tb_fwd(T c, T xm, T xp, T ym, T yp, T zm, T zp, T f
 }
 
 template <typename T>
-__device__ __forceinline__ T tb_adj(T c, T xm, T xp, T ym, T yp, T zm, T zp, T uq, T C0, T C1, double &sa,
-                                    double &sb) {
+__device__ __forceinline__ T tb_adj(T c, T xm, T xp, T ym, T yp, T zm, T zp, T uq, T C0, T C1, bool add,
+                                    double &sa, double &sb) {
     const T s6 = ((xm + xp) + (ym + yp)) + (zm + zp);
     const T lapn = fma(T(-6), c, s6);
     T acc = fma(C0, lapn, c);
     acc = fma(-(C1 * uq) * uq, c, acc);
-    const double du = (double)uq;
-    sa = (double)lapn * du;
-    sb = (double)c * (du * du * du);
+    if (add) {
+        const double du = (double)uq;
+        sa = fma((double)lapn, du, sa);
+        sb = fma((double)c, du * du * du, sb);
+    }
     return acc;
 }
 
@@ -212,7 +244,7 @@ __global__ void __launch_bounds__(NT) tb2_kernel(TbArgs a) {
 #pragma unroll
         for (int k = 0; k < kTbKmax; ++k) {
             if ((flags[k] & 2u) && gofs[k] >= 0 && zr >= 0)
-                tb_load<T, VEC>(d[k], QA + (int64_t)zr * sz + gofs[k]);
+                tb_load_nt<T, VEC>(d[k], QA + (int64_t)zr * sz + gofs[k]);
             else
                 tb_zero<T, VEC>(d[k]);
         }
@@ -221,7 +253,7 @@ __global__ void __launch_bounds__(NT) tb2_kernel(TbArgs a) {
 #pragma unroll
         for (int k = 0; k < kTbKmax; ++k) {
             if ((flags[k] & 4u) && zq >= 0 && zq < nz)
-                tb_load<T, VEC>(d[k], QB + (int64_t)zq * sz + gofs[k]);
+                tb_load_nt<T, VEC>(d[k], QB + (int64_t)zq * sz + gofs[k]);
             else
                 tb_zero<T, VEC>(d[k]);
         }
@@ -309,13 +341,8 @@ __global__ void __launch_bounds__(NT) tb2_kernel(TbArgs a) {
                     const T xm = e == 0 ? lft : c[e > 0 ? e - 1 : 0];
                     const T xp = e == VEC - 1 ? rgt : c[e + 1 < VEC ? e + 1 : e];
                     if constexpr (ADJ) {
-                        double sa, sb;
                         bn[k][e] = tb_adj<T>(c[e], xm, xp, ym[e], yp[e], am[k][e], ap[k][e], qac[k][e], C0, C1,
-                                             sa, sb);
-                        if (sum_here) {
-                            e1 += sa;
-                            r1 += sb;
-                        }
+                                             sum_here, e1, r1);
                     } else {
                         bn[k][e] = tb_fwd<T>(c[e], xm, xp, ym[e], yp[e], am[k][e], ap[k][e], qac[k][e], C0, C1,
                                              C2);
@@ -324,15 +351,15 @@ __global__ void __launch_bounds__(NT) tb2_kernel(TbArgs a) {
             }
             tb_store<T, VEC>(L1w + o - nx, bn[k]);
             if constexpr (MID)
-                if (sum_here) tb_store<T, VEC>(M + (int64_t)q * sz + gofs[k], bn[k]);
+                if (sum_here) tb_store_nt<T, VEC>(M + (int64_t)q * sz + gofs[k], bn[k]);
             if constexpr (RED && !ADJ) {
                 if (sum_here) {
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) {
                         const double d = (double)bn[k][e];
-                        e1 += d * d;
+                        e1 = fma(d, d, e1);
                         const double dd = d - (double)c[e];
-                        r1 += dd * dd;
+                        r1 = fma(dd, dd, r1);
                     }
                 }
             }
@@ -357,35 +384,32 @@ __global__ void __launch_bounds__(NT) tb2_kernel(TbArgs a) {
                     const T xm = e == 0 ? lft : c[e > 0 ? e - 1 : 0];
                     const T xp = e == VEC - 1 ? rgt : c[e + 1 < VEC ? e + 1 : e];
                     if constexpr (ADJ) {
-                        double sa, sb;
                         res[e] = tb_adj<T>(c[e], xm, xp, ym[e], yp[e], bm[k][e], bn[k][e], qbm[k][e], C0, C1,
-                                           sa, sb);
-                        e2 += sa;
-                        r2 += sb;
+                                           true, e2, r2);
                     } else {
                         res[e] = tb_fwd<T>(c[e], xm, xp, ym[e], yp[e], bm[k][e], bn[k][e], qbm[k][e], C0, C1,
                                            C2);
                     }
                 }
-                tb_store<T, VEC>(O + (int64_t)(q - 1) * sz + gofs[k], res);
+                tb_store_nt<T, VEC>(O + (int64_t)(q - 1) * sz + gofs[k], res);
                 if constexpr (LAM) {
                     // running sum of the adjoint inputs, in step order:
                     // lam = (lam + lambda_{t+1}) + lambda_t (level 0 at q-1 is in am)
                     T *lp = static_cast<T *>(a.lam) + (int64_t)(q - 1) * sz + gofs[k];
                     T lv[VEC];
                     if (a.lam_first) tb_zero<T, VEC>(lv);
-                    else tb_load<T, VEC>(lv, lp);
+                    else tb_load_nt<T, VEC>(lv, lp);
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) lv[e] = (lv[e] + am[k][e]) + c[e];
-                    tb_store<T, VEC>(lp, lv);
+                    tb_store_nt<T, VEC>(lp, lv);
                 }
                 if constexpr (RED && !ADJ) {
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) {
                         const double d = (double)res[e];
-                        e2 += d * d;
+                        e2 = fma(d, d, e2);
                         const double dd = d - (double)c[e];
-                        r2 += dd * dd;
+                        r2 = fma(dd, dd, r2);
                     }
                 }
             }
