@@ -60,9 +60,10 @@ def parse():
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--seed", type=int, default=0)
-    p.add_argument("--forms", choices=["main", "all", "jacobi", "generated"], default="all",
-                   help="main: the headline only; all: every form; jacobi / generated: the Jacobi "
-                        "forms or the fusing compiler's forms only (no headline line; for profiling)")
+    p.add_argument("--forms", choices=["main", "all", "jacobi", "generated", "ceiling", "adjoint"], default="all",
+                   help="main: the headline only; all: every form; jacobi / generated / ceiling / adjoint: "
+                        "the Jacobi forms, the fusing compiler's forms, the streaming ceiling or the adjoint "
+                        "kernel forms only (no headline line; for profiling)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-errors", action="store_true",
                    help="skip the per-form error check against the oracle (run after the CPU baseline)")
@@ -225,6 +226,82 @@ def form_errors(dev, u0, f64, u0_h, f_h, coeffs, bc, ref64) -> dict:
         del u
     errs["bounds"] = {"f64": 1e-12, "f32": 1e-5}
     return errs
+
+
+def stream_ceiling(dev, stream, reps: int = 20) -> dict:
+    """HBM bandwidth a plain streaming kernel reaches on this GPU (the
+    library's dcp_stream_probe over 1 GiB buffers): copy, two reads + one
+    write (the stencil's traffic shape), read and fill, each with ordinary
+    and with streaming (non-temporal) loads and stores; GB/s of bytes moved."""
+    import ctypes
+    import torch
+
+    from paper_2107_00555_amd import _lib
+    nbytes = 1 << 30
+    a = torch.rand(nbytes // 8, dtype=torch.float64, device=dev)
+    b = torch.rand(nbytes // 8, dtype=torch.float64, device=dev)
+    o = torch.empty(nbytes // 8, dtype=torch.float64, device=dev)
+    L = _lib.lib()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    out = {}
+    for kind, name, moved in ((0, "copy", 2), (1, "two_reads_one_write", 3), (2, "read", 1), (3, "fill", 1)):
+        for nt in (0, 1):
+            def call():
+                _lib.check("dcp_stream_probe", L.dcp_stream_probe(kind, nt, ctypes.c_void_p(a.data_ptr()),
+                                                                  ctypes.c_void_p(b.data_ptr()),
+                                                                  ctypes.c_void_p(o.data_ptr()), nbytes, sp))
+            ms, _, _ = timed(call, reps, 3, stream)
+            gbs = moved * nbytes / (ms / reps * 1e-3) / 1e9
+            out[f"{name}{'_nt' if nt else ''}"] = round(gbs, 1)
+    del a, b, o
+    torch.cuda.empty_cache()
+    out["unit"] = "GB/s"
+    return out
+
+
+def adjoint_forms(dev, stream, u0, f64, coeffs, bc, kk) -> dict:
+    """The adjoint kernel on the headline grid, both dtypes: 10 adjoint steps
+    from checkpoints of every step (no recomputation), alone and with the
+    running sum for dL/df and dL/dgamma."""
+    import torch
+
+    from paper_2107_00555_amd import _lib, api
+    nz, ny, nx = u0.shape
+    N = u0.numel()
+    forms = {}
+    for name, dtype in (("f64", torch.float64), ("f32", torch.float32)):
+        S = 8 if dtype == torch.float64 else 4
+        Ta = 10
+        fld = u0.to(dtype)
+        ff = f64.to(dtype)
+        ua = fld.clone()
+        ck = api.run(ua, ff, coeffs, Ta, bc, norms=False, ckpt_every=1)["ckpt"]
+        lam = (ua - fld).contiguous()
+        wsa = api.workspace(_lib.workspace_bytes(_lib.OP_ADJOINT, 0 if S == 8 else 1, nx, ny, nz,
+                                                 T=Ta, ckpt_every=1, tblock=3), dev)
+        g = torch.empty_like(lam)
+        log(f"timing adjoint kernel {name}")
+        ms_a, _, _ = timed(lambda: api.adjoint_run(ck, 1, ff, lam, coeffs, Ta, bc, ws=wsa, grad_u0=g),
+                           kk, 1, stream)
+        ms_a /= kk
+        # two adjoint steps per pass (the default): a pass reads lambda_{t+1},
+        # u_t and u_{t-1} and writes lambda_{t-1}, 2*S bytes per point update;
+        # "effective" prices every update at the one-step 3*S
+        glups = N * Ta / (ms_a / 1e3) / 1e9
+        forms[f"adjoint_{name}"] = {"glups": round(glups, 3), "ms_per_step": round(ms_a / Ta, 4),
+                                    "effective_hbm_frac": round(glups * 3 * S / HBM_PEAK_GBS, 4),
+                                    "hbm_frac_per_launch": round(glups * 2 * S / HBM_PEAK_GBS, 4)}
+        # the same steps also accumulating the sum of the adjoint inputs
+        # (dL/df, dL/dgamma): one more read and write of a field per pass
+        log(f"timing adjoint kernel {name} with dL/df and dL/dgamma")
+        ms_al, _, _ = timed(lambda: api.adjoint_run(ck, 1, ff, lam, coeffs, Ta, bc, ws=wsa, grad_u0=g,
+                                                    want_f=True, want_gamma=True), kk, 1, stream)
+        ms_al /= kk
+        forms[f"adjoint_{name}_with_f_gamma"] = {"glups": round(N * Ta / (ms_al / 1e3) / 1e9, 3),
+                                                 "ms_per_step": round(ms_al / Ta, 4)}
+        del ck, wsa, g, lam, ua, fld, ff
+        torch.cuda.empty_cache()
+    return forms
 
 
 def jacobi_forms(args, dev, stream) -> dict:
@@ -410,6 +487,9 @@ def main():
     if args.forms == "jacobi":
         print(json.dumps({"forms": {"jacobi": jacobi_forms(args, dev, stream)}, "data": "synthetic"}), flush=True)
         return
+    if args.forms == "ceiling":
+        print(json.dumps({"streaming_ceiling": stream_ceiling(dev, stream)}), flush=True)
+        return
     nx = ny = nz = 512
     N = nx * ny * nz
     T = 100
@@ -427,6 +507,17 @@ def main():
         print(json.dumps({"forms": {"generated": generated_forms(args, dev, stream, u0, f64, coeffs, bc)},
                           "data": "synthetic"}), flush=True)
         return
+    if args.calibrate_copy:
+        # the library's own copy kernel, 1 GiB read + 1 GiB write: a dcp_run of
+        # one step with a checkpoint every step copies u into slot 0 first
+        uc = u0.clone()
+        api.run(uc, f64, coeffs, 1, bc, norms=False, ckpt_every=1)
+        torch.cuda.synchronize()
+        del uc
+    if args.forms == "adjoint":
+        print(json.dumps({"forms": adjoint_forms(dev, stream, u0, f64, coeffs, bc, max(1, min(args.steps, 3))),
+                          "data": "synthetic"}), flush=True)
+        return
 
     # ---------------------------------------------------------- headline
     ws = api.workspace(_lib.workspace_bytes(_lib.OP_RUN, _lib.F64, nx, ny, nz, T=T, norms=True,
@@ -435,14 +526,6 @@ def main():
 
     def fused_step():
         res["out"] = api.run(u, f64, coeffs, T, bc, impl="fused", tblock=args.tblock, norms=True, ws=ws)
-
-    if args.calibrate_copy:
-        # the library's own copy kernel, 1 GiB read + 1 GiB write: a dcp_run of
-        # one step with a checkpoint every step copies u into slot 0 first
-        uc = u0.clone()
-        api.run(uc, f64, coeffs, 1, bc, norms=False, ckpt_every=1)
-        torch.cuda.synchronize()
-        del uc
 
     if args.tblock not in (1, 2, 3):
         raise SystemExit("--tblock must be 1, 2 or 3")
@@ -508,6 +591,10 @@ def main():
 
     # ------------------------------------------------------- other forms
     if args.forms == "all":
+        log("streaming ceiling of this GPU (dcp_stream_probe)")
+        ceil = stream_ceiling(dev, stream)
+        out["roofline"]["streaming_ceiling_gbs"] = ceil
+        out["roofline"]["frac_of_streaming_ceiling"] = round(achieved / ceil["two_reads_one_write_nt"], 4)
         forms = {}
         out["forms"] = forms
         kk = max(1, min(args.steps, 3))
@@ -609,41 +696,15 @@ def main():
             torch.cuda.empty_cache()
 
         # adjoint kernel alone: k = 1 (no recomputation), 10 steps
-        for name, dtype, fld, ff in (("f64", torch.float64, u0, f64), ("f32", torch.float32, u32, f32)):
-            S = 8 if dtype == torch.float64 else 4
-            Ta = 10
-            ua = fld.clone().to(dtype)
-            ck = api.run(ua, ff, coeffs, Ta, bc, norms=False, ckpt_every=1)["ckpt"]
-            lam = (ua - fld.to(dtype)).contiguous()
-            wsa = api.workspace(_lib.workspace_bytes(_lib.OP_ADJOINT, 0 if S == 8 else 1, nx, ny, nz,
-                                                     T=Ta, ckpt_every=1), dev)
-            g = torch.empty_like(lam)
-            log(f"timing adjoint kernel {name}")
-            ms_a, _, _ = timed(lambda: api.adjoint_run(ck, 1, ff, lam, coeffs, Ta, bc, ws=wsa, grad_u0=g),
-                               kk, 1, stream)
-            ms_a /= kk
-            # two adjoint steps per pass (the default): a pass reads lambda_{t+1},
-            # u_t and u_{t-1} and writes lambda_{t-1}, 2*S bytes per point update;
-            # "effective" prices every update at the one-step 3*S
-            forms[f"adjoint_{name}"] = {"glups": round(glups(ms_a, Ta), 3), "ms_per_step": round(ms_a / Ta, 4),
-                                        "effective_hbm_frac": round(frac(ms_a, 3 * S, Ta), 4),
-                                        "hbm_frac_per_launch": round(frac(ms_a, 2 * S, Ta), 4)}
-            # the same steps also accumulating the sum of the adjoint inputs
-            # (dL/df, dL/dgamma): one more read and write of a field per pass
-            log(f"timing adjoint kernel {name} with dL/df and dL/dgamma")
-            ms_al, _, _ = timed(lambda: api.adjoint_run(ck, 1, ff, lam, coeffs, Ta, bc, ws=wsa, grad_u0=g,
-                                                        want_f=True, want_gamma=True), kk, 1, stream)
-            ms_al /= kk
-            forms[f"adjoint_{name}_with_f_gamma"] = {"glups": round(glups(ms_al, Ta), 3),
-                                                     "ms_per_step": round(ms_al / Ta, 4)}
-            del ck, wsa, g, lam, ua
+        forms.update(adjoint_forms(dev, stream, u0, f64, coeffs, bc, kk))
 
         # end-to-end gradient, float64: forward T=100 with checkpoints every 10, then adjoint
         kck = 10
         ug = u0.clone()
         ck = torch.empty((T // kck, nz, ny, nx), dtype=torch.float64, device=dev)
         wsf = api.workspace(_lib.workspace_bytes(_lib.OP_RUN, _lib.F64, nx, ny, nz, T=T, tblock=2), dev)
-        wsa = api.workspace(_lib.workspace_bytes(_lib.OP_ADJOINT, _lib.F64, nx, ny, nz, T=T, ckpt_every=kck), dev)
+        wsa = api.workspace(_lib.workspace_bytes(_lib.OP_ADJOINT, _lib.F64, nx, ny, nz, T=T, ckpt_every=kck,
+                                                 tblock=3), dev)
         g = torch.empty_like(u0)
 
         def grad_step():
@@ -692,7 +753,7 @@ def main():
             gck = torch.empty((api.num_slots(Tg, kg), gz, gy, gx), dtype=tdt, device=dev)
             gwsf = api.workspace(_lib.workspace_bytes(_lib.OP_RUN, code, gx, gy, gz, T=Tg, tblock=3), dev)
             gwsa = api.workspace(_lib.workspace_bytes(_lib.OP_ADJOINT, code, gx, gy, gz, T=Tg, ckpt_every=kg,
-                                                      tblock=2), dev)
+                                                      tblock=3), dev)
             gg = torch.empty_like(gu0)
             glam = torch.empty_like(gu0)
 
@@ -744,7 +805,8 @@ def main():
         log(f"timing gradient f64 T={Tr}: checkpoint every {kr} steps")
         ck = torch.empty(((Tr + kr - 1) // kr, nz, ny, nx), dtype=torch.float64, device=dev)
         wsf = api.workspace(_lib.workspace_bytes(_lib.OP_RUN, _lib.F64, nx, ny, nz, T=Tr, tblock=2), dev)
-        wsa = api.workspace(_lib.workspace_bytes(_lib.OP_ADJOINT, _lib.F64, nx, ny, nz, T=Tr, ckpt_every=kr), dev)
+        wsa = api.workspace(_lib.workspace_bytes(_lib.OP_ADJOINT, _lib.F64, nx, ny, nz, T=Tr, ckpt_every=kr,
+                                                 tblock=3), dev)
 
         def uni_grad():
             ug.copy_(u0)

@@ -38,9 +38,10 @@
  *   by the caller.  `coeffs` is a HOST pointer read during the call only.
  *   The library never allocates or frees device memory: scratch space comes
  *   from the caller's workspace `ws` of `ws_bytes` bytes (size it with
- *   dcp_workspace_bytes; ws may be NULL when that size is 0).  The library
- *   holds no global state; calls on different streams with disjoint
- *   buffers may run concurrently.
+ *   dcp_workspace_bytes; ws may be NULL when that size is 0).  Apart from
+ *   the fixed scratch of dcp_step_fused_noalloc (below), the library holds
+ *   no global state; calls on different streams with disjoint buffers may
+ *   run concurrently.
  *
  * Execution.  Work is enqueued on `stream` (a hipStream_t; NULL is the
  *   default stream) and the call returns without synchronising.  Results,
@@ -59,9 +60,9 @@
  *
  * Tuning.  The tile and pass choices are the library's own.  For tuning
  * runs only, the environment variables DCP_TILE_SHAPE, DCP_TILE_ZC,
- * DCP_TB_CFG, DCP_TBK_CFG, DCP_FUSE_ZR, DCP_J1_K, DCP_J2_CFG and DCP_J2_MODE
- * force a tiling or schedule; they are read at each call and honoured only
- * while DCP_TUNING=1 is set as well.  A forced choice computes the same
+ * DCP_TB_CFG, DCP_TBK_CFG, DCP_TBK_SBLK, DCP_FUSE_ZR, DCP_J1_K, DCP_J2_CFG
+ * and DCP_J2_MODE force a tiling or schedule; they are read at each call
+ * and honoured only while DCP_TUNING=1 is set as well.  A forced choice computes the same
  * fields bit for bit; the double norms and sums may differ in rounding (their
  * summation order follows the tiles).
  */
@@ -247,14 +248,15 @@ int dcp_run_plan(int dtype, int impl, int64_t nx, int64_t ny, int64_t nz,
  * kernel, then one fused adjoint kernel per step applies J_t^T (L is
  * symmetric under both boundary rules, so L^T is the same 7-point gather)
  * and accumulates the two parameter sums in double.
- * With tblock = 2, two adjoint steps (and two recomputed forward steps)
- * share one pass over memory where the grid allows it; adjoint steps are
- * paired by global parity, (2m+1, 2m), independently of k.
+ * With tblock >= 2, two adjoint steps share one pass over memory where the
+ * grid allows whole-row tiles (adjoint steps are paired by global parity,
+ * (2m+1, 2m), independently of k), and the recomputed forward steps take
+ * passes of up to tblock steps, every state stored (as dcp_run plans them).
  *   ckpt        [ceil(T/k) fields] in: as written by dcp_run (same T, k,
  *               coefficients, boundary and dtype)
  *   f      [N]  in
  *   lam_T  [N]  in: dL/du_T
- *   tblock      1 or 2 (see above; same meaning as in dcp_run)
+ *   tblock      1, 2 or 3 (see above)
  *   grad_u0 [N] out: dL/du_0 (must not overlap ckpt, f, lam_T or ws)
  *   grad_ab [2] out, double: {dL/dalpha, dL/dbeta}, reduced in a fixed order,
  *               so for a given tblock the result does not depend on k bit
@@ -346,7 +348,7 @@ int dcp_jacobi_2d(int32_t tsteps, double *A, double *B, int64_t n0,
  *   grad_f.  Writes *bytes (host pointer).
  * dcp_revolve_forward: T steps in place on u (u_0 in, u_T out), as dcp_run
  *   computes them (bitwise the same u_T), saving u_0 and the snapshots the
- *   reverse sweep starts from in ws.  tblock as in dcp_run (1 or 2).
+ *   reverse sweep starts from in ws.  tblock as in dcp_run (1, 2 or 3).
  * dcp_revolve_adjoint: the same outputs as dcp_adjoint_run (grad_u0,
  *   grad_ab, optional grad_f and grad_gamma), from lam_T = dL/du_T and the
  *   workspace of the forward call (same T, nslots, coefficients, boundary
@@ -444,6 +446,22 @@ int dcp_fuse_run(dcp_fused *program, const void *const *inputs,
                  const double *params, void *const *outputs, int64_t nx,
                  int64_t ny, int64_t nz, int bc, void *ws, size_t ws_bytes,
                  void *stream);
+
+/*
+ * Streaming probe: one launch of a plain streaming kernel over device
+ * buffers, to measure the HBM bandwidth such a kernel reaches on this GPU
+ * (the practical ceiling for the kernels above; not part of the program).
+ *   kind  0: out = a (copy); 1: out = a + b (two reads, one write);
+ *         2: read a (out receives at most one 16-byte flag per workgroup,
+ *         65536 of them, and only for non-finite data); 3: fill out
+ *   nt    nonzero: loads and stores carry the streaming (non-temporal) hint
+ *   bytes size of each buffer, a multiple of 16; kind 2 needs at least
+ *         1 MiB and out of 1 MiB
+ * Buffers are 16-byte aligned device arrays of doubles; out must not
+ * overlap a or b.  Errors: DCP_E_ARG, DCP_E_NULL, DCP_E_ALIAS, DCP_E_HIP.
+ */
+int dcp_stream_probe(int kind, int nt, const void *a, const void *b,
+                     void *out, size_t bytes, void *stream);
 
 /* Static, NUL-terminated description of a dcp_status value. */
 const char *dcp_status_string(int status);

@@ -106,6 +106,8 @@ def lib() -> ctypes.CDLL:
     L.dcp_jacobi_1d.restype = c_int
     L.dcp_jacobi_2d.argtypes = [i32, vp, vp, i64, i64, i32, vp, sz, vp]
     L.dcp_jacobi_2d.restype = c_int
+    L.dcp_stream_probe.argtypes = [c_int, c_int, vp, vp, vp, sz, vp]
+    L.dcp_stream_probe.restype = c_int
     _lib = L
     return L
 

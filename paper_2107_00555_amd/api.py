@@ -158,8 +158,8 @@ def run(u: torch.Tensor, f: torch.Tensor, coeffs, T: int, bc, impl="fused", tblo
     """T steps in place on u.  Returns a dict with 'energy' and 'resid'
     (float64 [T] tensors, or None) and 'ckpt' (tensor of ceil(T/k) fields
     shaped (slots, nz, ny, nx), or None when ckpt_every == 0).  tblock
-    defaults to 2 (two steps per pass where the grid allows it) for the fused
-    form and 1 for the unfused one."""
+    defaults to 3 (up to three steps per pass where the grid allows it) for
+    the fused form and 1 for the unfused one."""
     u = _field("u", u)
     f = _field("f", f, u)
     dt = _dtype_code(u)
@@ -167,7 +167,7 @@ def run(u: torch.Tensor, f: torch.Tensor, coeffs, T: int, bc, impl="fused", tblo
     c = Coeffs.make(coeffs)
     ic = impl_code(impl)
     if tblock is None:
-        tblock = 2 if ic == FUSED else 1
+        tblock = 3 if ic == FUSED else 1
     wsb = _lib.workspace_bytes(OP_RUN, dt, nx, ny, nz, T=T, tblock=tblock, norms=norms, impl=ic)
     ws = _ws(ws, wsb, u.device)
     energy = torch.empty(max(T, 0), dtype=torch.float64, device=u.device) if norms else None
@@ -184,7 +184,7 @@ def run(u: torch.Tensor, f: torch.Tensor, coeffs, T: int, bc, impl="fused", tblo
 
 
 def adjoint_run(ckpt: torch.Tensor | None, ckpt_every: int, f: torch.Tensor, lam_T: torch.Tensor,
-                coeffs, T: int, bc, tblock: int = 2, ws: torch.Tensor | None = None,
+                coeffs, T: int, bc, tblock: int = 3, ws: torch.Tensor | None = None,
                 grad_u0: torch.Tensor | None = None, want_f: bool = False, want_gamma: bool = False):
     """Gradient through T fused steps from dcp_run's checkpoints.
     Returns (dL/du0, float64 tensor [dL/dalpha, dL/dbeta]), or with
@@ -222,7 +222,7 @@ def adjoint_run(ckpt: torch.Tensor | None, ckpt_every: int, f: torch.Tensor, lam
         out["gamma"] = gg[0]
     return out
 
-def revolve_forward(u: torch.Tensor, f: torch.Tensor, coeffs, T: int, bc, nslots: int, tblock: int = 2,
+def revolve_forward(u: torch.Tensor, f: torch.Tensor, coeffs, T: int, bc, nslots: int, tblock: int = 3,
                     reserve_sum: bool = False) -> torch.Tensor:
     """T steps in place on u with binomial checkpointing snapshots; returns
     the workspace tensor the matching revolve_adjoint call needs (keep it
@@ -242,7 +242,7 @@ def revolve_forward(u: torch.Tensor, f: torch.Tensor, coeffs, T: int, bc, nslots
 
 
 def revolve_adjoint(ws: torch.Tensor, f: torch.Tensor, lam_T: torch.Tensor, coeffs, T: int, bc, nslots: int,
-                    tblock: int = 2, want_f: bool = False, want_gamma: bool = False):
+                    tblock: int = 3, want_f: bool = False, want_gamma: bool = False):
     """The gradient from revolve_forward's workspace; returns like adjoint_run."""
     lam_T = _field("lam_T", lam_T)
     f = _field("f", f, lam_T)

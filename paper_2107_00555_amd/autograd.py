@@ -30,7 +30,7 @@ def _as(meta, v: torch.Tensor) -> torch.Tensor:
 
 class RD3D(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, u0, f, alpha, beta, gamma, dt, h, T, bc, ckpt_every, tblock=2, revolve_slots=0):
+    def forward(ctx, u0, f, alpha, beta, gamma, dt, h, T, bc, ckpt_every, tblock=3, revolve_slots=0):
         coeffs = dict(alpha=_scalar(alpha), beta=_scalar(beta), gamma=_scalar(gamma),
                       h=float(h), dt=float(dt))
         k = max(1, int(ckpt_every))
@@ -80,7 +80,7 @@ class RD3D(torch.autograd.Function):
         return gu, gf, ga, gb, gg, None, None, None, None, None, None, None
 
 
-def rd3d(u0, f, alpha, beta, gamma, dt, h, T, bc, ckpt_every=10, tblock=2, revolve_slots=0):
+def rd3d(u0, f, alpha, beta, gamma, dt, h, T, bc, ckpt_every=10, tblock=3, revolve_slots=0):
     """u_T after T fused steps from u0, differentiable in u0, f, alpha, beta
     and gamma.  revolve_slots > 0: binomial checkpointing with that many
     snapshots instead of a checkpoint every ckpt_every steps."""

@@ -34,7 +34,7 @@ COMMON = [
 ]
 
 SOURCES = ["dcp_kernels.hip", "dcp_tblock.hip", "dcp_tbk.hip", "dcp_jacobi.hip", "dcp_api.cpp", "dcp_revolve.cpp",
-           "dcp_fuse.cpp"]
+           "dcp_fuse.cpp", "dcp_probe.hip"]
 
 
 def _compile(src: str) -> str:

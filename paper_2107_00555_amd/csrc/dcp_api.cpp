@@ -157,8 +157,9 @@ constexpr size_t kLdsMax = 160 * 1024;
 // Plan of a B-step pass (dcp_tbk.hip).  DCP_TBK_CFG="wc,ty,lanes" restricts
 // the planner to segments of wc chunks (a value covering the row: whole
 // rows), slabs of ty rows and 1024 or 512 lanes; 0 leaves a choice to the
-// planner.  A tuning override only: every choice computes the same states
-// bit for bit (the norms' summation order follows the tiles).
+// planner.  DCP_TBK_SBLK sets the slabs per block of the tile order.
+// Tuning overrides only: every choice computes the same states bit for bit
+// (the norms' summation order follows the tiles).
 bool tbk_for(int dtype, const Geo &g, int B, bool vok, size_t lds_limit, TbkTile *t) {
     int wc = 0, ty = 0, lanes = 1024;
     if (const char *e = tuning_env("DCP_TBK_CFG")) {
@@ -169,7 +170,12 @@ bool tbk_for(int dtype, const Geo &g, int B, bool vok, size_t lds_limit, TbkTile
             lanes = c == 512 ? 512 : 1024;
         }
     }
-    return tbk_plan(dtype, B, g.nx, g.ny, g.nz, vok, lds_limit, lanes, wc, ty, t);
+    if (!tbk_plan(dtype, B, g.nx, g.ny, g.nz, vok, lds_limit, lanes, wc, ty, t)) return false;
+    if (const char *e = tuning_env("DCP_TBK_SBLK")) {
+        const int h = std::atoi(e);
+        if (h > 0) t->sblk = h < t->nslab ? h : t->nslab;
+    }
+    return true;
 }
 
 int layout_run(int dtype, int impl, const Geo &g, int32_t T, int32_t tblock, bool norms, RunWs *w) {
@@ -414,7 +420,21 @@ hipError_t tbk_fwd_pass(int dtype, int bc, const Geo &g, const dcp_coeffs &c, co
     a.wc = tk.wc;
     a.halo = tk.halo;
     a.chf = tk.chf;
+    a.sblk = tk.sblk;
     return launch_tbk(dtype, bc, part != nullptr, tk, a, st);
+}
+
+// One forward pass of len (1, 2 or 3) steps without norms, u -> out, in the
+// kernel `pp` plans for that length; mid[i] (when not null) receives the
+// state after i+1 steps of a multi-step pass.
+hipError_t fwd_pass(int dtype, int bc, const Geo &g, const dcp_coeffs &c, const Tile &t, const PassPlan &pp,
+                    int len, const void *u, const void *f, void *out, void *mid0, void *mid1, hipStream_t st) {
+    if (len == 3 || (len == 2 && !pp.use_tb)) {
+        void *mid[2] = {mid0, len == 3 ? mid1 : nullptr};
+        return tbk_fwd_pass(dtype, bc, g, c, len == 3 ? pp.k3 : pp.k2, u, f, out, mid, nullptr, st);
+    }
+    if (len == 2) return tb_fwd_pass(dtype, bc, g, c, pp.tb, u, f, out, mid0, nullptr, nullptr, st);
+    return fused_step(dtype, bc, g, c, t, u, f, out, nullptr, st);
 }
 
 bool vec_ok_for(int dtype, const Geo &g, std::initializer_list<const void *> ptrs) {
@@ -527,14 +547,14 @@ struct RevBufs {
 };
 
 // n fused steps from `from` into `to` (n >= 1; both distinct from the
-// scratch field), two per pass where the grid allows it, alternating between
-// `to` and the scratch so the last step lands in `to`.
-int rev_advance(int dtype, int bc, const Geo &g, const dcp_coeffs &c, const Tile &t, bool use_tb,
-                const TbTile &tb, const void *f, const void *from, void *to, void *scratch, int64_t n,
-                hipStream_t st) {
+// scratch field), in the passes of `pp` (up to three steps each where the
+// grid allows it), alternating between `to` and the scratch so the last pass
+// lands in `to`.
+int rev_advance(int dtype, int bc, const Geo &g, const dcp_coeffs &c, const Tile &t, const PassPlan &pp,
+                const void *f, const void *from, void *to, void *scratch, int64_t n, hipStream_t st) {
     std::vector<int> lens;
     for (int64_t left = n; left > 0;) {
-        const int k = (use_tb && left >= 2) ? 2 : 1;
+        const int k = pp.len_at(0, left > 3 ? 3 : (int32_t)left);
         lens.push_back(k);
         left -= k;
     }
@@ -542,12 +562,8 @@ int rev_advance(int dtype, int bc, const Geo &g, const dcp_coeffs &c, const Tile
     const size_t L = lens.size();
     for (size_t i = 0; i < L; ++i) {
         void *out = ((L - 1 - i) % 2 == 0) ? to : scratch;
-        if (lens[i] == 2) {
-            if (tb_fwd_pass(dtype, bc, g, c, tb, cur, f, out, nullptr, nullptr, nullptr, st) != hipSuccess)
-                return DCP_E_HIP;
-        } else if (fused_step(dtype, bc, g, c, t, cur, f, out, nullptr, st) != hipSuccess) {
+        if (fwd_pass(dtype, bc, g, c, t, pp, lens[i], cur, f, out, nullptr, nullptr, st) != hipSuccess)
             return DCP_E_HIP;
-        }
         cur = out;
     }
     return DCP_OK;
@@ -877,6 +893,7 @@ int dcp_adjoint_run(int dtype, const void *ckpt, int32_t ckpt_every, const void 
     const dcp_coeffs &c = *coeffs;
     TbTile tb{};
     const bool use_tb = plan_tb(dtype, g, tblock, vok, &tb) && tb.nblk <= stride;
+    const PassPlan fpp = plan_passes(dtype, DCP_FUSED, g, T, tblock, vok, false, 0);  // recomputation
 
     StencilArgs aa{};
     aa.nx = g.nx;
@@ -912,18 +929,16 @@ int dcp_adjoint_run(int dtype, const void *ckpt, int32_t ckpt_every, const void 
     for (int32_t cs = nslots - 1; cs >= 0; --cs) {
         const int32_t t0 = cs * ckpt_every;
         const int32_t t1 = (t0 + ckpt_every < T) ? t0 + ckpt_every : T;
-        // recompute the states u_{t0+1} .. u_{t1-1} of this segment
+        // recompute the states u_{t0+1} .. u_{t1-1} of this segment (u_{t0+j}
+        // into seg(j-1)), up to three steps per pass, every state stored
         const void *prev = slot(cs);
         for (int32_t j = 1; j < t1 - t0;) {
-            if (use_tb && j + 1 < t1 - t0) {
-                DCP_TRY(tb_fwd_pass(dtype, bc, g, c, tb, prev, f, seg(j), seg(j - 1), nullptr, nullptr, st));
-                prev = seg(j);
-                j += 2;
-            } else {
-                DCP_TRY(fused_step(dtype, bc, g, c, t, prev, f, seg(j - 1), nullptr, st));
-                prev = seg(j - 1);
-                j += 1;
-            }
+            const int32_t left = t1 - t0 - j;
+            const int len = fpp.len_at(0, left > 3 ? 3 : left);
+            DCP_TRY(fwd_pass(dtype, bc, g, c, t, fpp, len, prev, f, seg(j + len - 2),
+                             len >= 2 ? seg(j - 1) : nullptr, len == 3 ? seg(j) : nullptr, st));
+            prev = seg(j + len - 2);
+            j += len;
         }
         // u_t for t in [t0, t1], the upper end being the next slot
         auto state = [&](int32_t tt) -> const void * {
@@ -1024,8 +1039,7 @@ int dcp_revolve_forward(int dtype, void *u, const void *f, int64_t nx, int64_t n
     bool vok = vec_ok_for(dtype, g, {u, f, B.buf(kRvOrigin), B.buf(nslots), scratch});
     for (int32_t i = 0; i < nslots; ++i) vok = vok && aligned16(B.buf(i));
     const Tile t = pick_tile(dtype, g, vok);
-    TbTile tb{};
-    const bool use_tb = plan_tb(dtype, g, tblock, vok, &tb);
+    const PassPlan pp = plan_passes(dtype, DCP_FUSED, g, T, tblock, vok, false, 0);
     const dcp_coeffs &c = *coeffs;
     DCP_TRY(launch_ew(dtype, EW_COPY, u, nullptr, B.buf(kRvOrigin), 0.0, g.n, vok, st));
     // the schedule's opening chain of advances, u_0 -> ... -> u_{T-1}, stores
@@ -1033,8 +1047,8 @@ int dcp_revolve_forward(int dtype, void *u, const void *f, int64_t nx, int64_t n
     int32_t last = kRvOrigin;
     for (const RvOp &op : ops) {
         if (op.kind != kRvAdvance) break;
-        if ((rc = rev_advance(dtype, bc, g, c, t, use_tb, tb, f, B.buf(op.src), B.buf(op.dst), scratch,
-                              op.t1 - op.t0, st)))
+        if ((rc = rev_advance(dtype, bc, g, c, t, pp, f, B.buf(op.src), B.buf(op.dst), scratch, op.t1 - op.t0,
+                              st)))
             return rc;
         last = op.dst;
     }
@@ -1092,8 +1106,7 @@ int dcp_revolve_adjoint(int dtype, const void *f, const void *lam_T, int64_t nx,
                                      lam[0], lam[1], lsum});
     for (int32_t i = 0; i < nslots; ++i) vok = vok && aligned16(B.buf(i));
     const Tile t = pick_tile(dtype, g, vok);
-    TbTile tb{};
-    const bool use_tb = plan_tb(dtype, g, tblock, vok, &tb);
+    const PassPlan pp = plan_passes(dtype, DCP_FUSED, g, T, tblock, vok, false, 0);
     const dcp_coeffs &c = *coeffs;
     double *partials = reinterpret_cast<double *>(at(ws, w.partials));
     double *sums = reinterpret_cast<double *>(at(ws, w.sums));
@@ -1118,7 +1131,7 @@ int dcp_revolve_adjoint(int dtype, const void *f, const void *lam_T, int64_t nx,
     for (size_t i = i0; i < ops.size(); ++i) {
         const RvOp &op = ops[i];
         if (op.kind == kRvAdvance) {
-            if ((rc = rev_advance(dtype, bc, g, c, t, use_tb, tb, f, B.buf(op.src), B.buf(op.dst), scratch,
+            if ((rc = rev_advance(dtype, bc, g, c, t, pp, f, B.buf(op.src), B.buf(op.dst), scratch,
                                   op.t1 - op.t0, st)))
                 return rc;
             continue;

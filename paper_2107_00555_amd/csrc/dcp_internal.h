@@ -14,7 +14,7 @@ namespace dcp {
 
 // Tuning overrides: environment variables that force a tiling or a pass
 // schedule (DCP_TILE_SHAPE, DCP_TILE_ZC, DCP_TB_CFG, DCP_TBK_CFG,
-// DCP_FUSE_ZR, DCP_J1_K, DCP_J2_CFG, DCP_J2_MODE).  They are honoured only
+// DCP_TBK_SBLK, DCP_FUSE_ZR, DCP_J1_K, DCP_J2_CFG, DCP_J2_MODE).  They are honoured only
 // while DCP_TUNING=1 is also set, so a stray variable alone changes nothing.
 // Every forced choice computes the same fields; a norm's summation order
 // follows the tiles.
@@ -132,12 +132,17 @@ struct TbkArgs {
     int64_t nx, ny, nz;
     double c0, c1, c2;
     int ty, nslab, nseg, zc, wc, halo, chf;
+    int sblk;  // slabs per block of the tile order (see TbkTile)
 };
 struct TbkTile {
     int B, vec, ty, nt, km;
     bool seg;             // x-segments with a halo (false: whole rows)
     int wc, halo, chf;    // segment chunks, halo chunks per side, frame chunks per row
     int nseg, nslab, zc, nruns, nblk;
+    // Tile order within a z-run: blocks of sblk slabs, each block taking all
+    // its segments (slab fastest), so that the tiles one XCD runs together
+    // (a contiguous range) are neighbours along x and y.
+    int sblk;
     size_t lds_bytes;
 };
 // Plans a B-step pass; false if the kernel does not apply (no 16-byte lanes,

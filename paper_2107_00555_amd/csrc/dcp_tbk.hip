@@ -16,9 +16,10 @@
 //     on each side (at least B points), so rows of any length keep B steps
 //     per pass;
 //   * one workgroup per CU (256 in all, numbered so an XCD holds a
-//     contiguous run of tiles): the tiles of a z-run are resident together
-//     and march up z side by side, so their halo rows and chunks are read
-//     while the neighbour reads them and are served by the XCD's L2;
+//     contiguous block of slabs across all segments): the tiles of a z-run
+//     are resident together and march up z side by side, so their halo rows
+//     and chunks are read while the neighbour reads them and are served by
+//     the XCD's L2;
 //   * each lane owns up to KM chunks of the level-0 frame (ty + 2B rows x the
 //     tile's chunks); level 0 (u_t) of the current plane sits in LDS, levels
 //     1..B-1 of their two most recent planes sit in LDS (double buffers),
@@ -167,8 +168,12 @@ __global__ void __launch_bounds__(NT) tbk_kernel(TbkArgs a) {
     const int ncol = a.nslab * a.nseg;
     const int cb = Lb % ncol;
     const int zrun = Lb / ncol;
-    const int seg = cb / a.nslab;
-    const int slab = cb % a.nslab;
+    // blocks of sblk slabs (the last may be shorter), segments within a block
+    const int blk = cb / (a.nseg * a.sblk);
+    const int rem = cb - blk * a.nseg * a.sblk;
+    const int hb = min(a.sblk, a.nslab - blk * a.sblk);
+    const int seg = rem / hb;
+    const int slab = blk * a.sblk + rem % hb;
     const int y0 = slab * TY;
     const int z0 = zrun * a.zc;
     const int z1 = min(nz, z0 + a.zc);
@@ -508,6 +513,14 @@ bool tbk_plan(int dtype, int B, int64_t nx, int64_t ny, int64_t nz, bool vec_ok,
                 t->nruns = (int)runs;
                 t->nblk = (int)(cols * runs);
                 t->lds_bytes = lds;
+                // the 256 workgroups go round-robin to the 8 XCDs and are
+                // renumbered so each XCD holds a contiguous run of tiles:
+                // make that run a block of slabs across all segments, so the
+                // halo rows and chunks a tile shares with its neighbours are
+                // read through the same L2 (measured at 512^3 FP64: reads per
+                // pass 2.55 -> 2.12 GiB, 1.06x the algorithmic 2 GiB)
+                int64_t per = (t->nblk + 7) / 8 / nseg;
+                t->sblk = (int)(per < 1 ? 1 : per > nslab ? nslab : per);
             }
         }
     }

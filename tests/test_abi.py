@@ -345,3 +345,20 @@ def test_tuning_overrides_need_the_master_switch(L, monkeypatch):
     assert forced["segmented"] == 1 and forced["tile_rows"] == 4 and forced["lanes"] == 512, forced
     monkeypatch.setenv("DCP_TUNING", "0")
     assert L.run_plan(L.F64, 512, 512, 512, 100, 3) == default
+
+
+def test_stream_probe_argument_errors(L):
+    lib = L.lib()
+    P = ctypes.c_void_p
+    a, b, o = P(0x10000000), P(0x50000000), P(0x90000000)
+    MiB = 1 << 20
+    assert lib.dcp_stream_probe(4, 0, a, b, o, MiB, None) == -5
+    assert lib.dcp_stream_probe(-1, 0, a, b, o, MiB, None) == -5
+    assert lib.dcp_stream_probe(0, 0, a, b, o, MiB + 8, None) == -5
+    assert lib.dcp_stream_probe(0, 0, a, b, o, 0, None) == -5
+    assert lib.dcp_stream_probe(2, 0, a, b, o, 4096, None) == -5        # read needs >= 1 MiB
+    assert lib.dcp_stream_probe(1, 0, a, None, o, MiB, None) == -1
+    assert lib.dcp_stream_probe(0, 0, None, b, o, MiB, None) == -1
+    assert lib.dcp_stream_probe(3, 0, None, None, None, MiB, None) == -1
+    assert lib.dcp_stream_probe(0, 0, P(0x10000008), b, o, MiB, None) == -5   # misaligned
+    assert lib.dcp_stream_probe(0, 0, a, b, P(0x10000000 + MiB // 2), MiB, None) == -7

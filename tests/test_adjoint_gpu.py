@@ -59,7 +59,7 @@ def test_adjoint_f32_matches_oracle(bc):
     assert gab[1] == pytest.approx(wb, rel=1e-5)
 
 
-@pytest.mark.parametrize("tblock", [1, 2])
+@pytest.mark.parametrize("tblock", [1, 2, 3])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_gradient_is_bitwise_independent_of_checkpoint_interval(dtype, tblock):
     api = _api()
@@ -161,13 +161,16 @@ def test_two_step_adjoint_equals_single_steps(shape, T, k, bc, dtype):
     fd = to_dev(f, dtype)
     say("two-step adjoint", shape, T, k, bc, dtype)
     res = {}
-    for tb in (1, 2):
+    for tb in (1, 2, 3):
         u = to_dev(u0, dtype)
         out = api.run(u, fd, BASE, T, bc, tblock=tb, norms=False, ckpt_every=k)
         res[tb] = api.adjoint_run(out["ckpt"], k, fd, to_dev(lam, dtype), BASE, T, bc, tblock=tb)
     torch.cuda.synchronize()
     assert torch.equal(res[1][0], res[2][0])
     assert torch.allclose(res[1][1], res[2][1], rtol=1e-12, atol=0)
+    # three-step recomputation passes store the same states: the gradient
+    # equals the two-step one bit for bit (the adjoint passes are the same)
+    assert torch.equal(res[3][0], res[2][0]) and torch.equal(res[3][1], res[2][1])
 
 
 @pytest.mark.parametrize("bc", [0, 1])
@@ -183,3 +186,30 @@ def test_two_step_adjoint_matches_oracle(bc):
     gab = to_host(gab)
     assert_rel("dL/dalpha", gab[0], wa, 1e-12)
     assert_rel("dL/dbeta", gab[1], wb, 1e-12)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("bc", [0, 1])
+def test_wide_rows_recompute_with_multi_step_passes(bc, dtype):
+    # rows too long for whole-row tiles: the recomputation takes multi-step
+    # passes over x-segments and the adjoint steps run one per pass, so the
+    # whole gradient equals the one-step form bit for bit
+    api = _api()
+    shape, T, k = (1030 if dtype == torch.float64 else 2052, 11, 9), 10, 5
+    u0, f = rand_fields(shape, 950 + bc)
+    lam = np.random.default_rng(95).uniform(-1, 1, u0.shape)
+    fd = to_dev(f, dtype)
+    say("wide-row recomputation", shape, bc, dtype)
+    res = {}
+    for tb in (1, 3):
+        u = to_dev(u0, dtype)
+        out = api.run(u, fd, BASE, T, bc, tblock=tb, norms=False, ckpt_every=k)
+        res[tb] = api.adjoint_run(out["ckpt"], k, fd, to_dev(lam, dtype), BASE, T, bc, tblock=tb)
+    torch.cuda.synchronize()
+    assert torch.equal(res[1][0], res[3][0]) and torch.equal(res[1][1], res[3][1])
+    if dtype == torch.float64:
+        want, wa, wb = oracle.adjoint(u0, f, lam, BASE, T, bc)
+        assert_normwise("dL/du0", to_host(res[3][0]), want, 1e-12)
+        gab = to_host(res[3][1])
+        assert_rel("dL/dalpha", gab[0], wa, 1e-12)
+        assert_rel("dL/dbeta", gab[1], wb, 1e-12)

@@ -65,7 +65,7 @@ def test_gamma_f_gradients_bitwise_independent_of_k_and_tblock(dtype):
     lam = np.random.default_rng(9).uniform(-1, 1, u0.shape)
     say("gamma/f k and tblock independence", dtype)
     ref = None
-    for tblock in (1, 2):
+    for tblock in (1, 2, 3):
         for k in (1, 2, 3, 10, 25):
             r = full_grad(u0, f, lam, T, bc, k, tblock, dtype)
             if ref is None:

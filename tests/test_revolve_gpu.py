@@ -34,7 +34,7 @@ def both(u0, f, lam, T, bc, nslots, tblock, dtype=torch.float64, k=3):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-@pytest.mark.parametrize("tblock", [1, 2])
+@pytest.mark.parametrize("tblock", [1, 2, 3])
 @pytest.mark.parametrize("bc", [0, 1])
 @pytest.mark.parametrize("T,nslots", [(1, 1), (2, 0), (7, 0), (9, 1), (10, 2), (23, 3), (40, 5), (6, 12)])
 def test_revolve_equals_uniform_checkpoints_bitwise(T, nslots, bc, tblock, dtype):

@@ -124,3 +124,16 @@ def test_every_tiling_gives_the_same_states(monkeypatch, wc, ty, lanes):
                 _same_as_single_steps(shape, dtype, bc, 8, 3, 1400 + ty + shape[0])
     print(f"forced tiling {wc},{ty},{lanes}: three-step passes in {used} of 4 cases")
 
+
+
+@pytest.mark.parametrize("sblk", [1, 3, 5, 7, 1000])
+def test_tile_order_blocks_cover_every_tile(monkeypatch, sblk):
+    # the tile order takes blocks of sblk slabs across all segments (the last
+    # block shorter when sblk does not divide the slab count); every order
+    # must visit each tile once: states equal one-step runs bit for bit
+    say("tile order", sblk)
+    monkeypatch.setenv("DCP_TUNING", "1")
+    monkeypatch.setenv("DCP_TBK_SBLK", str(sblk))
+    for shape, dtype in (((1030, 37, 11), torch.float64), ((600, 29, 9), torch.float32), ((96, 37, 11), torch.float64)):
+        for bc in BCS:
+            _same_as_single_steps(shape, dtype, bc, 8, 3, 1500 + sblk + shape[1])
