@@ -3,7 +3,7 @@
 // kernels are compared with).  Not part of the reaction-diffusion program.
 //
 // Each kernel walks its buffers in 16-byte vectors with a grid-stride loop
-// (65536 workgroups of 512 lanes); `nt` selects loads and stores with the
+// (65536 workgroups of 1024 lanes); `nt` selects loads and stores with the
 // streaming (non-temporal) hint, the form the stencil kernels use for data
 // they touch once.
 #include <hip/hip_runtime.h>
@@ -28,7 +28,7 @@ __device__ __forceinline__ void pstore(probe_v2 *p, probe_v2 v) {
 // kind 0: out = a; 1: out = a + b; 2: read a (one flag written per
 // workgroup only if a value never produced by the generator appears); 3: out = c
 template <int KIND, bool NT>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(1024)
     probe_kernel(const probe_v2 *__restrict__ a, const probe_v2 *__restrict__ b, probe_v2 *__restrict__ o,
                  int64_t n) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -47,7 +47,7 @@ __global__ void __launch_bounds__(512)
 
 template <int KIND>
 hipError_t probe_launch(bool nt, const void *a, const void *b, void *o, int64_t n, hipStream_t st) {
-    const dim3 grid(65536), block(512);
+    const dim3 grid(65536), block(1024);
     const auto *A = static_cast<const probe_v2 *>(a);
     const auto *Bp = static_cast<const probe_v2 *>(b);
     auto *O = static_cast<probe_v2 *>(o);

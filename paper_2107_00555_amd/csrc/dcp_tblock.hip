@@ -8,8 +8,8 @@
 // only within distance 1, and step t+1 is recomputed on a one-row halo.
 //
 // Layout of the work:
-//   * a workgroup (512 lanes with four 16-byte chunks each, or 1024 with
-//     two; one workgroup per CU) owns full x-rows: a slab of TY rows x all
+//   * a workgroup (1024 lanes with two 16-byte chunks each; one workgroup
+//     per CU) owns full x-rows: a slab of TY rows x all
 //     nx points x zc planes, so there is no x-halo at all and the periodic
 //     x-wrap stays inside the slab;
 //   * the grid has one workgroup per CU (256), so every slab of a z-run is
@@ -283,11 +283,12 @@ __global__ void __launch_bounds__(NT) tb2_kernel(TbArgs a) {
 
     // register queues: level 0 at q-1, q+1 and the prefetched q+2; level 1 at
     // q-2 and q; level-1 point operand at q and the prefetched q+1; level-2
-    // point operand at q-1 (and, for the adjoint, the prefetched q); the
+    // point operand at q-1 (the forward's is the level-1 operand of the
+    // previous plane; the adjoint's is loaded in the same iteration); the
     // centres live in LDS
     T am[kTbKmax][VEC], ap[kTbKmax][VEC], an[kTbKmax][VEC];
     T bm[kTbKmax][VEC], bn[kTbKmax][VEC];
-    T qbm[kTbKmax][VEC], qac[kTbKmax][VEC], qan[kTbKmax][VEC], qbn[kTbKmax][VEC];
+    T qbm[kTbKmax][VEC], qac[kTbKmax][VEC], qan[kTbKmax][VEC];
     double e1 = 0.0, r1 = 0.0, e2 = 0.0, r2 = 0.0;
 
     T ac0[kTbKmax][VEC];  // level 0 at the first plane, written to LDS in the first iteration
@@ -301,7 +302,6 @@ __global__ void __launch_bounds__(NT) tb2_kernel(TbArgs a) {
     for (int k = 0; k < kTbKmax; ++k) {
         tb_zero<T, VEC>(bm[k]);
         tb_zero<T, VEC>(qbm[k]);
-        tb_zero<T, VEC>(qbn[k]);
         if (flags[k] & 1u) tb_store<T, VEC>(L0 + lofs[k], ac0[k]);
     }
 
@@ -312,8 +312,12 @@ __global__ void __launch_bounds__(NT) tb2_kernel(TbArgs a) {
         if (more) {
             load_u(q + 2, an);
             load_qa(q + 1, qan);
-            if constexpr (ADJ) load_qb(q, qbn);
         }
+        // the adjoint's level-2 point operand, u_(t-1) at plane q-1, is loaded
+        // here for stage B of this iteration (its latency hides behind stage
+        // A) rather than an iteration ahead: one queue slot fewer, so the
+        // 1024-lane build stays within 128 VGPRs
+        if constexpr (ADJ) load_qb(q - 1, qbm);
         __syncthreads();
 
         // stage A: level 1 at plane q
@@ -427,8 +431,7 @@ __global__ void __launch_bounds__(NT) tb2_kernel(TbArgs a) {
         for (int k = 0; k < kTbKmax; ++k) {
             if (flags[k] & 1u) tb_store<T, VEC>(L0 + lofs[k], ap[k]);  // level 0 at q+1
             tb_copy<T, VEC>(ap[k], an[k]);
-            if constexpr (ADJ) tb_copy<T, VEC>(qbm[k], qbn[k]);
-            else tb_copy<T, VEC>(qbm[k], qac[k]);
+            if constexpr (!ADJ) tb_copy<T, VEC>(qbm[k], qac[k]);
             tb_copy<T, VEC>(qac[k], qan[k]);
         }
     }
@@ -504,18 +507,18 @@ hipError_t tb_launch_t(int op, int bc, bool reduce, bool mid, const TbTile &t, c
 }
 
 // Compiled configurations (slab rows, lanes, chunks per lane), in order of
-// preference: taller slabs recompute fewer halo rows.  Each chunk costs about
-// 40-50 VGPRs (eight or nine queued 16-byte vectors plus addressing).  512
-// lanes with four chunks each (2 waves per SIMD, up to 256 VGPRs) stay out of
-// scratch and measured faster than 1024 lanes with two chunks (128 VGPRs,
-// which spills in the adjoint): at 512^3, FP64 adjoint 305 vs 248 GLUP/s,
-// FP32 adjoint 611 vs 393.  8-row slabs fit rows of up to 170 chunks
+// preference: taller slabs recompute fewer halo rows.  1024 lanes with two
+// chunks each (four waves per SIMD, up to 128 VGPRs; every forward and
+// adjoint build stays out of scratch but the float periodic adjoint with the
+// running sum, 8 bytes).  512 lanes with four chunks (two waves per SIMD)
+// measured slower at 512^3: forward FP64 423 vs 455 GLUP/s, adjoint FP64
+// 326 vs 352, FP32 612 vs 689.  8-row slabs fit rows of up to 170 chunks
 // (FP32 nx <= 680), 4-row slabs up to 256 chunks (FP64 nx <= 512,
 // FP32 nx <= 1024); the LDS budget is checked separately.
 struct TbCfg {
     int ty, nt, km;
 };
-constexpr TbCfg kTbCfgs[] = {{8, 512, 4}, {4, 512, 4}, {8, 1024, 2}, {4, 1024, 2}};
+constexpr TbCfg kTbCfgs[] = {{8, 1024, 2}, {4, 1024, 2}};
 constexpr int kNumTbCfgs = sizeof(kTbCfgs) / sizeof(kTbCfgs[0]);
 
 }  // namespace
@@ -559,32 +562,13 @@ bool tb_plan(int dtype, int64_t nx, int64_t ny, int64_t nz, bool vec_ok, size_t 
 
 hipError_t launch_tb2(int dtype, int op, int bc, bool reduce, const TbTile &t, const TbArgs &a, hipStream_t st) {
     const bool mid = op == SOP_FWD && a.mid != nullptr;
-    bool n1024 = t.nt == 1024 && t.km == 2;
-    const bool n512 = t.nt == 512 && t.km == 4;
-    if (!n1024 && !n512) return hipErrorInvalidValue;
-    // The forward pass runs a planned 512-lane slab with 1024 lanes of two
-    // chunks instead: same rows, LDS and grid (both hold 2048 chunks), twice
-    // the waves per CU, and every forward build of it stays within 128 VGPRs
-    // without scratch; measured 7% faster at 512^3 in FP64 and FP32.  The
-    // adjoint keeps 512 lanes: its 1024-lane build spills under periodic
-    // boundaries and measured no faster (FP64) or slower (FP32).
-    const char *forced = tuning_env("DCP_TB_CFG");  // tuning runs only
-    if (op == SOP_FWD && n512 && !(forced && *forced) && t.lds_bytes >= (size_t)(1024 / 64) * 4 * sizeof(double))
-        n1024 = true;
+    if (t.nt != 1024 || t.km != 2) return hipErrorInvalidValue;
     if (dtype == 0) {
-        if (n1024) {
-            if (t.ty == 8) return tb_launch_t<double, 2, 8, 1024, 2>(op, bc, reduce, mid, t, a, st);
-            return tb_launch_t<double, 2, 4, 1024, 2>(op, bc, reduce, mid, t, a, st);
-        }
-        if (t.ty == 8) return tb_launch_t<double, 2, 8, 512, 4>(op, bc, reduce, mid, t, a, st);
-        return tb_launch_t<double, 2, 4, 512, 4>(op, bc, reduce, mid, t, a, st);
+        if (t.ty == 8) return tb_launch_t<double, 2, 8, 1024, 2>(op, bc, reduce, mid, t, a, st);
+        return tb_launch_t<double, 2, 4, 1024, 2>(op, bc, reduce, mid, t, a, st);
     }
-    if (n1024) {
-        if (t.ty == 8) return tb_launch_t<float, 4, 8, 1024, 2>(op, bc, reduce, mid, t, a, st);
-        return tb_launch_t<float, 4, 4, 1024, 2>(op, bc, reduce, mid, t, a, st);
-    }
-    if (t.ty == 8) return tb_launch_t<float, 4, 8, 512, 4>(op, bc, reduce, mid, t, a, st);
-    return tb_launch_t<float, 4, 4, 512, 4>(op, bc, reduce, mid, t, a, st);
+    if (t.ty == 8) return tb_launch_t<float, 4, 8, 1024, 2>(op, bc, reduce, mid, t, a, st);
+    return tb_launch_t<float, 4, 4, 1024, 2>(op, bc, reduce, mid, t, a, st);
 }
 
 }  // namespace dcp

@@ -137,3 +137,29 @@ def test_tile_order_blocks_cover_every_tile(monkeypatch, sblk):
     for shape, dtype in (((1030, 37, 11), torch.float64), ((600, 29, 9), torch.float32), ((96, 37, 11), torch.float64)):
         for bc in BCS:
             _same_as_single_steps(shape, dtype, bc, 8, 3, 1500 + sblk + shape[1])
+
+
+@pytest.mark.parametrize("cfg", [0, 1])
+def test_every_two_step_configuration(monkeypatch, cfg):
+    # the two-step kernel's compiled slab heights (8 and 4 rows, 1024 lanes),
+    # forced: forward states and dL/du0 equal one-step passes bit for bit
+    api = _api()
+    say("two-step configuration", cfg)
+    monkeypatch.setenv("DCP_TUNING", "1")
+    monkeypatch.setenv("DCP_TB_CFG", str(cfg))
+    for dtype in (torch.float64, torch.float32):
+        for bc in BCS:
+            shape = (96, 37, 11)
+            _same_as_single_steps(shape, dtype, bc, 8, 2, 1600 + cfg)
+            u0, f = rand_fields(shape, 1700 + cfg)
+            lam = np.random.default_rng(17).uniform(-1, 1, u0.shape)
+            fd = to_dev(f, dtype)
+            res = {}
+            for tb in (1, 2):
+                u = to_dev(u0, dtype)
+                out = api.run(u, fd, BASE, 7, bc, tblock=tb, norms=False, ckpt_every=3)
+                res[tb] = api.adjoint_run(out["ckpt"], 3, fd, to_dev(lam, dtype), BASE, 7, bc, tblock=tb)
+            torch.cuda.synchronize()
+            assert torch.equal(res[1][0], res[2][0])
+            rt = 1e-12 if dtype == torch.float64 else 1e-6
+            assert torch.allclose(res[1][1], res[2][1], rtol=rt, atol=0)
