@@ -60,8 +60,8 @@
  *
  * Tuning.  The tile and pass choices are the library's own.  For tuning
  * runs only, the environment variables DCP_TILE_SHAPE, DCP_TILE_ZC,
- * DCP_TB_CFG, DCP_TBK_CFG, DCP_TBK_SBLK, DCP_FUSE_ZR, DCP_J1_K, DCP_J2_CFG
- * and DCP_J2_MODE force a tiling or schedule; they are read at each call
+ * DCP_TB_CFG, DCP_TBK_CFG, DCP_TBK_SBLK, DCP_FUSE_ZR, DCP_J1_K, DCP_J2_CFG,
+ * DCP_J2_MODE and DCP_J2M_CPL force a tiling or schedule; they are read at each call
  * and honoured only while DCP_TUNING=1 is set as well.  A forced choice computes the same
  * fields bit for bit; the double norms and sums may differ in rounding (their
  * summation order follows the tiles).

@@ -14,8 +14,9 @@ namespace dcp {
 
 // Tuning overrides: environment variables that force a tiling or a pass
 // schedule (DCP_TILE_SHAPE, DCP_TILE_ZC, DCP_TB_CFG, DCP_TBK_CFG,
-// DCP_TBK_SBLK, DCP_FUSE_ZR, DCP_J1_K, DCP_J2_CFG, DCP_J2_MODE).  They are honoured only
-// while DCP_TUNING=1 is also set, so a stray variable alone changes nothing.
+// DCP_TBK_SBLK, DCP_FUSE_ZR, DCP_J1_K, DCP_J2_CFG, DCP_J2_MODE,
+// DCP_J2M_CPL).  They are honoured only while DCP_TUNING=1 is also set, so a
+// stray variable alone changes nothing.
 // Every forced choice computes the same fields; a norm's summation order
 // follows the tiles.
 inline const char *tuning_env(const char *name) {

@@ -406,6 +406,264 @@ __global__ void __launch_bounds__(64 * W, MINW) j2_kernel(J2Args a) {
     }
 }
 
+// ------------------------------------------- jacobi_2d, marching down rows
+// The form for large arrays.  A workgroup is one wave and owns a strip of
+// 64*CPL columns (CPL per lane; the first and last hh are halo, recomputed)
+// and a segment of rows, and marches down the rows applying NH half-steps in
+// one pass: at step q, level s (the arrays after s half-steps; odd levels are
+// B, even levels A) is computed for row q - s + 1, from level s - 1 of rows
+// q - s .. q - s + 2, the last of which level s - 1 has just computed.  For
+// every level each lane keeps three rows of its columns in registers, so the
+// rows above and below come from the lane itself and the columns left and
+// right from the adjacent lanes (DPP): no LDS exchange and no barrier.  Row x
+// of every level lives in register slot x mod 3; the loop is unrolled three
+// times, so the slots are fixed at compile time and no register is copied as
+// the march advances.  Compared with the region tiles above, only the columns
+// carry a halo, and the rows before a segment are recomputed once (NH - 1
+// rows per level).
+// Loads of level 0 are issued D rows ahead of use.  They read clamped rows
+// and columns, so they need no guard: a value read for a row or column
+// outside the array only ever feeds a boundary cell of the array, which is
+// replaced by its fixed value (a select, so whatever was computed there is
+// dropped), or another cell outside the array.  The array's boundary cells
+// keep their values at every level: the two boundary rows (both arrays) are
+// kept in LDS when the march reads them, and so are the boundary column's
+// values (both arrays) of the rows in flight, in a small ring.  Requires n1
+// even, hh even and 16-byte aligned arrays.
+typedef double j2m_v2 __attribute__((ext_vector_type(2)));
+
+struct J2MArgs {
+    const double *ain, *bfix;  // level 0 (A); B's values (its boundary cells never change)
+    double *aout, *bout;
+    int64_t n0, n1;
+    int hh, strips, seg_rows, write_b;
+};
+
+template <int NH, int CPL, int D>
+__global__ void __launch_bounds__(64) j2m_kernel(J2MArgs a) {
+    static_assert(CPL == 2 || CPL == 4, "two or four columns per lane");
+    static_assert(D == 1 || D == 3, "the prefetch ring must divide the unroll");
+    constexpr int C = 64 * CPL, NP = CPL / 2, RING = NH + 4;
+    __shared__ double fixrow[2][2][C];     // [row 0 / row n0-1][A / B][column]
+    __shared__ double fixcol[RING][2][2];  // [ring slot][column 0 / n1-1][A / B]
+    const int lane = threadIdx.x;
+    const int b = j_xcd_remap(blockIdx.x, gridDim.x);
+    const int strip = b % a.strips, seg = b / a.strips;  // strips fastest: neighbours share halos in L2
+    const int n0 = (int)a.n0;  // < 2^30, checked by the host (so are the row indices below)
+    const int n1 = (int)a.n1;
+    const int ci = CPL * lane;  // column offset in the strip
+    const int gc = strip * (C - 2 * a.hh) - a.hh + ci;  // column of this lane's first value (even)
+    // pair p (columns gc+2p, gc+2p+1): in the array both or neither; its load
+    // column, clamped into the array; whether this strip stores it
+    int colp[NP];
+    bool inp[NP], ownp[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const int c = gc + 2 * p;
+        colp[p] = min(max(c, 0), n1 - 2);
+        inp[p] = c >= 0 && c < n1;
+        ownp[p] = inp[p] && ci + 2 * p >= a.hh && ci + 2 * p < C - a.hh;
+    }
+    // boundary columns: column 0 is this lane's value -gc (even) and column
+    // n1 - 1 its value n1 - 1 - gc (odd) when that lies in the lane
+    const int k0 = -gc;
+    const bool bc0 = k0 >= 0 && k0 < CPL;
+    const int k1 = n1 - 1 - gc;
+    const bool bc1 = k1 >= 1 && k1 < CPL;
+    uint64_t keep[CPL];
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) keep[k] = __builtin_amdgcn_ballot_w64(gc + k == 0 || gc + k == n1 - 1);
+    const bool edge = __builtin_amdgcn_ballot_w64(bc0 || bc1) != 0;  // uniform over the wave
+    const int R0 = seg * a.seg_rows;
+    const int R1 = min(n0, R0 + a.seg_rows);
+    const bool rowedge = R0 - NH <= 0 || R1 + NH > n0 - 1;  // rows in flight include a boundary row
+    if (R0 >= R1) return;  // a segment past the last row (no barrier below)
+
+    auto row_of = [&](const double *base, int r) {  // uniform row start, the row clamped into the array
+        return base + (int64_t)min(max(r, 0), n0 - 1) * n1;
+    };
+    auto load_row = [&](int r, double (&x)[CPL]) {
+        const double *rp = row_of(a.ain, r);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const j2m_v2 v = *reinterpret_cast<const j2m_v2 *>(rp + colp[p]);
+            x[2 * p] = v.x;
+            x[2 * p + 1] = v.y;
+        }
+    };
+    // record the fixed values of row r (x: its level-0 values; fb0, fb1: B
+    // at columns 0 and n1 - 1) in ring slot rs
+    auto keep_fixed = [&](int r, int rs, const double (&x)[CPL], double fb0, double fb1) {
+        if (edge) {  // uniform
+            if (bc0) {
+                double v = x[0];
+#pragma unroll
+                for (int k = 2; k < CPL; k += 2)
+                    if (k0 == k) v = x[k];
+                fixcol[rs][0][0] = v;
+                fixcol[rs][0][1] = fb0;
+            }
+            if (bc1) {
+                double v = x[1];
+#pragma unroll
+                for (int k = 3; k < CPL; k += 2)
+                    if (k1 == k) v = x[k];
+                fixcol[rs][1][0] = v;
+                fixcol[rs][1][1] = fb1;
+            }
+        }
+        if (rowedge && (r == 0 || r == n0 - 1)) {  // uniform
+            const int w = r == 0 ? 0 : 1;
+            const double *bp = row_of(a.bfix, r);
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const j2m_v2 v = *reinterpret_cast<const j2m_v2 *>(bp + colp[p]);
+                fixrow[w][1][ci + 2 * p] = v.x;
+                fixrow[w][1][ci + 2 * p + 1] = v.y;
+            }
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) fixrow[w][0][ci + k] = x[k];
+        }
+    };
+    auto wrap = [](int x) { return x >= RING ? x - RING : (x < 0 ? x + RING : x); };
+
+    double S[NH][3][CPL];  // [level][row slot: row mod 3, counted from q0][column]
+    double P[D][CPL];      // level-0 rows in flight
+    double PB[D][2];       // B at their boundary columns (edge waves)
+    const int q0 = R0 - NH + 1, qlast = R1 + NH - 2;
+    // level 0: rows q0 - 1 and q0 now, rows q0 + 1 .. q0 + D in flight
+    load_row(q0 - 1, S[0][2]);
+    load_row(q0, S[0][0]);
+    auto load_bfix = [&](int r, double (&fb)[2]) {
+        if (edge) {  // uniform
+            const double *bp = row_of(a.bfix, r);
+            fb[0] = bp[0];
+            fb[1] = bp[n1 - 1];
+        }
+    };
+    {
+        double fb[2][2] = {};
+        load_bfix(q0 - 1, fb[0]);
+        load_bfix(q0, fb[1]);
+        keep_fixed(q0 - 1, 0, S[0][2], fb[0][0], fb[0][1]);
+        keep_fixed(q0, 1, S[0][0], fb[1][0], fb[1][1]);
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        load_row(q0 + 1 + d, P[(1 + d) % D]);
+        PB[(1 + d) % D][0] = PB[(1 + d) % D][1] = 0.0;
+        load_bfix(q0 + 1 + d, PB[(1 + d) % D]);
+    }
+    int rn = 2;  // ring slot of row q + 1 at step q
+
+    // Step q at phase PH = (q - q0) mod 3.  GENERAL: levels still starting,
+    // boundary rows or columns in the wave, rows outside the segment; the
+    // plain form drops all of those checks (scalar work that would otherwise
+    // take issue slots from the update itself).
+    auto step = [&](int q, auto PH, auto GENERAL) {
+        constexpr int ph = decltype(PH)::value;
+        constexpr bool general = decltype(GENERAL)::value;
+        // level 0 takes row q + 1; row q + 1 + D is fetched into its place
+        double(&l0)[CPL] = S[0][(ph + 1) % 3];
+        double(&pf)[CPL] = P[(ph + 1) % D];
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) l0[k] = pf[k];
+        if (general) keep_fixed(q + 1, rn, l0, PB[(ph + 1) % D][0], PB[(ph + 1) % D][1]);
+        load_row(q + 1 + D, pf);
+        if (general) load_bfix(q + 1 + D, PB[(ph + 1) % D]);
+#pragma unroll
+        for (int s = 1; s <= NH; ++s) {
+            if (general && q < R0 - NH + 2 * s - 1) break;  // uniform: later levels start later still
+            const int r = q - s + 1;
+            // level s - 1 rows r - 1, r, r + 1 and the slot of row r
+            const int lo = ((ph - s) % 3 + 3) % 3, mid = ((ph - s + 1) % 3 + 3) % 3,
+                      hi = ((ph - s + 2) % 3 + 3) % 3;
+            const double(&in0)[CPL] = S[s - 1][lo];
+            const double(&in1)[CPL] = S[s - 1][mid];
+            const double(&in2)[CPL] = S[s - 1][hi];
+            const double wl = from_lower(in1[CPL - 1]);
+            const double er = from_upper(in1[0]);
+            double nv[CPL];
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) {
+                const double w = k ? in1[k - 1] : wl;
+                const double e = k < CPL - 1 ? in1[k + 1] : er;
+                nv[k] = kW2 * ((((in1[k] + w) + e) + in2[k]) + in0[k]);
+            }
+            const int arr = s & 1;  // 1: B
+            if (general) {
+                if (rowedge && (r == 0 || r == n0 - 1)) {  // uniform: a boundary row keeps its values
+                    const int w = r == 0 ? 0 : 1;
+#pragma unroll
+                    for (int k = 0; k < CPL; ++k) nv[k] = fixrow[w][arr][ci + k];
+                } else if (edge) {  // uniform: the boundary columns keep their values
+                    // (column 0 sits at an even place of a lane, column n1 - 1 at an odd one)
+                    const int rs = wrap(rn - s);
+                    const double f0 = fixcol[rs][0][arr], f1 = fixcol[rs][1][arr];
+#pragma unroll
+                    for (int k = 0; k < CPL; ++k) nv[k] = j_keep(keep[k], nv[k], (k & 1) ? f1 : f0);
+                }
+            }
+            if (s < NH) {
+#pragma unroll
+                for (int k = 0; k < CPL; ++k) S[s][mid][k] = nv[k];
+            }
+            // A's row r is in the segment on the plain path; B's row (the
+            // level before) is stored by the last pass only
+            if (s == NH && (!general || (r >= R0 && r < R1))) {
+                const int64_t ro = (int64_t)r * n1 + gc;
+#pragma unroll
+                for (int p = 0; p < NP; ++p)
+                    if (ownp[p])
+                        __builtin_nontemporal_store(j2m_v2{nv[2 * p], nv[2 * p + 1]},
+                                                    reinterpret_cast<j2m_v2 *>(a.aout + ro + 2 * p));
+            }
+            if (s == NH - 1 && a.write_b != 0 && r >= R0 && r < R1) {
+                const int64_t ro = (int64_t)r * n1 + gc;
+#pragma unroll
+                for (int p = 0; p < NP; ++p) {
+                    if (!ownp[p]) continue;
+                    const int64_t o = ro + 2 * p;
+                    if (a.write_b == 1) {
+                        __builtin_nontemporal_store(j2m_v2{nv[2 * p], nv[2 * p + 1]},
+                                                    reinterpret_cast<j2m_v2 *>(a.bout + o));
+                    } else if (r >= 1 && r <= n0 - 2) {  // B's interior only
+                        if (gc + 2 * p >= 1) a.bout[o] = nv[2 * p];
+                        if (gc + 2 * p + 1 <= n1 - 2) a.bout[o + 1] = nv[2 * p + 1];
+                    }
+                }
+            }
+        }
+        if (general) rn = wrap(rn + 1);
+    };
+    using P0 = std::integral_constant<int, 0>;
+    using P1 = std::integral_constant<int, 1>;
+    using P2 = std::integral_constant<int, 2>;
+    // The general steps: until every level has started (step q0 + 2 NH - 2,
+    // rounded up to a whole group of three), or to the end for waves holding
+    // a boundary row or column.  The plain steps carry on from there.  Loops
+    // run whole groups and the last one or two steps follow them, so every
+    // register keeps its place across the loop's back edge (a copy there
+    // would wait for the rows still in flight).
+    const int qg = (edge || rowedge) ? qlast + 1 : min(qlast + 1, q0 + (2 * NH - 2 + 2) / 3 * 3);
+    int qb = q0;
+    for (; qb < qg; qb += 3) {
+        step(qb, P0{}, std::true_type{});
+        if (qb + 1 < qg) step(qb + 1, P1{}, std::true_type{});
+        if (qb + 2 < qg) step(qb + 2, P2{}, std::true_type{});
+    }
+    if (qg == qlast + 1) return;
+    for (; qb + 3 <= qlast + 1; qb += 3) {
+        step(qb, P0{}, std::false_type{});
+        step(qb + 1, P1{}, std::false_type{});
+        step(qb + 2, P2{}, std::false_type{});
+    }
+    if (qb <= qlast) {
+        step(qb, P0{}, std::false_type{});
+        if (qb + 1 <= qlast) step(qb + 1, P1{}, std::false_type{});
+    }
+}
+
 // ------------------------------------------------------------- host side
 constexpr int kJ2C = 128;  // region columns (2D)
 constexpr int kJ1MaxTb = 256, kJ2MaxTb = 16;
@@ -463,6 +721,58 @@ int64_t j2_interior_tiles(int64_t n0, int64_t n1, int64_t hh, int rows, int64_t 
     return span(n0, ir, rows, tr) * span(n1, ic, 128, tc);
 }
 
+// The row-marching form (j2m_kernel): used for arrays that give it enough
+// waves with row segments of at least 8*NH rows, when n1 is even and the
+// arrays are 16-byte aligned; passes of 4 to 16 half-steps (even) that start
+// with B (whole time-loop iterations).  Four columns per lane (rows fetched
+// one ahead) for passes of up to 8 half-steps, else two (rows fetched three
+// ahead).  DCP_J2M_CPL = 2 or 4 picks the columns per lane (4 only up to 8
+// half-steps), DCP_J2_MODE = 3 forces the form where it applies, 1 or 2 the
+// region tiles (tuning runs only).
+struct J2MPlan {
+    bool use = false;
+    int cpl = 2;
+    int strips = 0, segs = 0, seg_rows = 0;
+};
+
+J2MPlan j2m_pick(int64_t n0, int64_t n1, int64_t hh) {
+    J2MPlan m;
+    m.cpl = hh <= 8 ? 4 : 2;
+    const char *fc = dcp::tuning_env("DCP_J2M_CPL");
+    if (fc && *fc) {
+        const int c = std::atoi(fc);
+        if (c == 2 || (c == 4 && hh <= 8)) m.cpl = c;
+    }
+    const int64_t C = 64 * m.cpl;
+    if (n0 < 3 || n1 < 3 || n0 >= ((int64_t)1 << 30) || n1 % 2 != 0 || hh % 2 != 0 || hh < 4 || hh > 16)
+        return m;
+    const int64_t strips = (n1 + (C - 2 * hh) - 1) / (C - 2 * hh);
+    const int64_t maxsegs = std::max<int64_t>(1, n0 / (8 * hh));
+    const int64_t segs = std::max<int64_t>(1, std::min<int64_t>(maxsegs, (16384 + strips - 1) / strips));
+    if (strips * segs > INT32_MAX / 2) return m;
+    m.strips = (int)strips;
+    m.segs = (int)segs;
+    m.seg_rows = (int)((n0 + segs - 1) / segs);
+    m.use = strips * segs >= 2048;
+    const char *fm = dcp::tuning_env("DCP_J2_MODE");
+    if (fm && *fm) m.use = std::atoi(fm) == 3;
+    return m;
+}
+
+// Instantiations: two columns per lane with rows fetched three ahead for
+// every pass depth, four columns per lane with rows fetched one ahead up to
+// eight half-steps (deeper ones spill).
+template <int NH>
+void j2m_launch_nh(const J2MPlan &mp, dim3 grid, hipStream_t sm, const J2MArgs &m) {
+    if constexpr (NH <= 8) {
+        if (mp.cpl == 4) {
+            hipLaunchKernelGGL((j2m_kernel<NH, 4, 1>), grid, dim3(64), 0, sm, m);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((j2m_kernel<NH, 2, 3>), grid, dim3(64), 0, sm, m);
+}
+
 J2Plan j2_pick(int64_t n0, int64_t n1, int64_t hh) {
     J2Plan p{1, false};
     int64_t all = 0;
@@ -515,13 +825,14 @@ int j_geo(int dims, int64_t n0, int64_t n1, JGeo *g) {
 
 // Half-steps per pass.  The defaults are the measured best on MI355X: in 1D
 // 64 for small arrays (the pass count is launch-bound) and 128 for large
-// ones; in 2D 12 (10-14 measured within a few percent at 1300^2 and 46800^2).
+// ones; in 2D 8 where the row-marching form applies, else 12 (10-14
+// measured within a few percent with the region tiles at 1300^2).
 int j_tblock(const JGeo &g, int32_t tblock, int *hp) {
     const int mx = g.dims == 1 ? kJ1MaxTb : kJ2MaxTb;
     if (tblock < 0 || tblock > mx) return DCP_E_ARG;
     if (tblock > 0) *hp = tblock;
     else if (g.dims == 1) *hp = g.count >= ((int64_t)1 << 22) ? 128 : 64;
-    else *hp = 12;
+    else *hp = j2m_pick(g.n0, g.n1, 8).use ? 8 : 12;
     return DCP_OK;
 }
 
@@ -722,12 +1033,33 @@ int dcp_jacobi_2d(int32_t tsteps, double *A, double *B, int64_t n0, int64_t n1, 
         }
         return hipGetLastError();
     };
+    const J2MPlan mp = j2m_pick(n0, n1, p.hh);
+    auto launch_march = [&](const J2MArgs &m, int nh) -> hipError_t {
+        const dim3 grid((unsigned)((int64_t)mp.strips * mp.segs));
+        switch (nh) {
+            case 4: j2m_launch_nh<4>(mp, grid, sm, m); break;
+            case 6: j2m_launch_nh<6>(mp, grid, sm, m); break;
+            case 8: j2m_launch_nh<8>(mp, grid, sm, m); break;
+            case 10: j2m_launch_nh<10>(mp, grid, sm, m); break;
+            case 12: j2m_launch_nh<12>(mp, grid, sm, m); break;
+            case 14: j2m_launch_nh<14>(mp, grid, sm, m); break;
+            default: j2m_launch_nh<16>(mp, grid, sm, m); break;
+        }
+        return hipGetLastError();
+    };
     return j_run_passes(g, p, A, B, ws,
                         [&](const double *ain, const double *bin, const double *bfix, double *aout, double *bout,
                             int nh, int ph, int wb) {
                             const bool v16 = (n1 % 2 == 0) && (p.hh % 2 == 0) &&
                                              ((uintptr_t)ain | (uintptr_t)bin | (uintptr_t)bfix |
                                               (uintptr_t)aout | (uintptr_t)bout) % 16 == 0;
+                            // whole iterations (B first, B's interior not read):
+                            // the row-marching form
+                            if (mp.use && v16 && p.whole && ph == 0 && nh >= 4 && nh <= 16 && nh % 2 == 0) {
+                                const J2MArgs m{ain, bfix, aout, bout, n0, n1, (int)p.hh, mp.strips, mp.seg_rows,
+                                                wb};
+                                return launch_march(m, nh);
+                            }
                             const J2Args a{ain, bin, bfix, aout, bout, n0, n1, inner_r, inner_c,
                                            (int)tiles_r, (int)tiles_c, (int)p.hh, nh, ph, wb, v16 ? 1 : 0,
                                            0, r_lo, r_hi, c_lo, c_hi};

@@ -95,6 +95,32 @@ def test_jacobi_2d_every_workgroup_shape(monkeypatch, mode, cfg, shape, tsteps, 
     assert_same(gpu_run(2, tsteps, A, B, tblock), oracle.jacobi_2d(tsteps, A, B), f"jacobi_2d cfg={cfg} mode={mode}")
 
 
+MARCH_CASES = [((300, 200), 9, 8), ((300, 200), 30, 8), ((257, 512), 14, 4), ((1300, 1300), 20, 0),
+               ((700, 900), 13, 6), ((3, 400), 6, 4), ((64, 130), 9, 12), ((1001, 258), 23, 10),
+               ((50, 2000), 11, 8), ((400, 116), 9, 8), ((400, 118), 7, 6), ((257, 511), 9, 8),
+               ((5, 6), 9, 4), ((129, 4), 5, 4), ((600, 1030), 17, 14), ((500, 778), 25, 16),
+               ((333, 262), 9, 16)]
+MARCH_CFGS = ["2", "4"]
+
+
+@pytest.mark.parametrize("cfg", MARCH_CFGS)
+@pytest.mark.parametrize("shape,tsteps,tblock", MARCH_CASES)
+def test_jacobi_2d_marching_form(monkeypatch, shape, tsteps, tblock, cfg):
+    """The row-marching form, forced where it applies (n1 even, whole
+    iterations per pass of 4..16 half-steps), with two or four columns per
+    lane (four only up to 8 half-steps): strips of columns with a halo
+    and segments of rows, one or many of each, the array's boundary rows and
+    columns inside and at the edges of strips (column n1 - 1 at either odd
+    place of a four-column run); an odd n1 falls back to the region tiles.
+    Bit for bit against the oracle."""
+    monkeypatch.setenv("DCP_TUNING", "1")
+    monkeypatch.setenv("DCP_J2_MODE", "3")
+    monkeypatch.setenv("DCP_J2M_CPL", cfg)
+    A, B = inputs.jacobi_fields(2, shape[0], seed=shape[0] + 3 * shape[1], n1=shape[1])
+    say(f"jacobi_2d marching shape={shape} tsteps={tsteps} tblock={tblock} cfg={cfg}")
+    assert_same(gpu_run(2, tsteps, A, B, tblock), oracle.jacobi_2d(tsteps, A, B), "jacobi_2d marching")
+
+
 @pytest.mark.parametrize("tblock", [0, 1, 256])
 def test_jacobi_1d_paper_size_full_run(tblock):
     w = inputs.JACOBI_WORKLOADS["jacobi_1d_paper"]
