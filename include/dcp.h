@@ -354,9 +354,15 @@ int dcp_jacobi_2d(int32_t tsteps, double *A, double *B, int64_t n0,
  *   workspace of the forward call (same T, nslots, coefficients, boundary
  *   and dtype).  The reverse sweep reuses the snapshot slots, so one
  *   forward call serves one adjoint call (run the forward again for
- *   another).  Adjoint steps run one per pass, so grad_u0, grad_ab,
- *   grad_f and grad_gamma equal dcp_adjoint_run's with tblock = 1 bit for
- *   bit; tblock applies to the recomputed forward steps.
+ *   another).  The fields grad_u0 and grad_f and the sum grad_gamma equal
+ *   dcp_adjoint_run's with tblock = 1 bit for bit; so does grad_ab with
+ *   tblock = 1.  tblock applies to the recomputed forward steps, and with
+ *   tblock >= 2 two consecutive adjoint steps whose states are both stored
+ *   run as one pass, whose per-step sums are added in another order (grad_ab
+ *   then differs from tblock = 1 by rounding only).  A one-step advance whose
+ *   state only the next adjoint step reads is folded into that step (the
+ *   state is recomputed at each point, bitwise as the advance computes it),
+ *   and a chain of one-step advances into fresh buffers runs as one pass.
  * Arguments, ownership and errors as for dcp_run / dcp_adjoint_run.
  */
 int dcp_revolve_workspace_bytes(int dtype, int64_t nx, int64_t ny,

@@ -548,13 +548,15 @@ struct RevBufs {
 
 // n fused steps from `from` into `to` (n >= 1; both distinct from the
 // scratch field), in the passes of `pp` (up to three steps each where the
-// grid allows it), alternating between `to` and the scratch so the last pass
-// lands in `to`.
+// grid allows it; four steps left go as two passes of two, which cost less
+// than three and one), alternating between `to` and the scratch so the last
+// pass lands in `to`.
 int rev_advance(int dtype, int bc, const Geo &g, const dcp_coeffs &c, const Tile &t, const PassPlan &pp,
                 const void *f, const void *from, void *to, void *scratch, int64_t n, hipStream_t st) {
     std::vector<int> lens;
     for (int64_t left = n; left > 0;) {
-        const int k = pp.len_at(0, left > 3 ? 3 : (int32_t)left);
+        int k = pp.len_at(0, left > 3 ? 3 : (int32_t)left);
+        if (left == 4 && k == 3 && pp.len_at(0, 2) == 2) k = 2;
         lens.push_back(k);
         left -= k;
     }
@@ -1122,32 +1124,115 @@ int dcp_revolve_adjoint(int dtype, const void *f, const void *lam_T, int64_t nx,
     aa.zc = t.zc;
     aa.nblk = t.nblk;
     aa.lam = lsum;
+    aa.c1f = c.dt * c.beta;  // the forward step's coefficients, for the fused recomputation
+    aa.c2f = c.dt * c.gamma;
+    // two adjoint steps per pass where both states are at hand (tblock >= 2)
+    TbTile tb{};
+    const bool use_tb = tblock >= 2 && plan_tb(dtype, g, tblock, vok, &tb) && tb.nblk <= stride;
+    TbArgs ta{};
+    ta.nx = g.nx;
+    ta.ny = g.ny;
+    ta.nz = g.nz;
+    ta.c0 = aa.c0;
+    ta.c1 = aa.c1;
+    ta.nslab = tb.nslab;
+    ta.zc = tb.zc;
+    ta.lam = lsum;
+    std::vector<int> step_nblk((size_t)T, t.nblk);
     const int adj_op = lsum ? SOP_ADJL : SOP_ADJ;
+    const int adj_rop = lsum ? SOP_ADJLR : SOP_ADJR;
     int lam_first = 1;
     const void *lcur = lam_T;
+    // A one-step advance whose result only the next adjoint step reads is
+    // folded into that step: the adjoint kernel recomputes u_s at each point
+    // from u_{s-1}, with the advance's arithmetic, instead of reading it.
+    auto fold = [&](size_t i) {
+        const RvOp &a = ops[i];
+        if (a.kind != kRvAdvance || a.t1 - a.t0 != 1 || i + 1 >= ops.size()) return false;
+        const RvOp &b = ops[i + 1];
+        if (b.kind != kRvAdjoint || b.src != a.dst || b.t0 != a.t1) return false;
+        for (size_t j = i + 2; j < ops.size(); ++j) {  // is the advance's buffer read again?
+            if (ops[j].src == a.dst) return false;
+            if (ops[j].kind == kRvAdvance && ops[j].dst == a.dst) break;
+        }
+        return true;
+    };
+    // A chain of one-step advances, each from the previous one's state into
+    // a buffer of its own, is one pass of two or three steps that stores
+    // every state it passes.
+    auto chain = [&](size_t i) {
+        size_t j = i;
+        while (j + 1 < ops.size() && j - i < 2) {
+            const RvOp &a = ops[j], &b = ops[j + 1];
+            if (b.kind != kRvAdvance || b.t1 - b.t0 != 1 || b.src != a.dst || b.t0 != a.t1) break;
+            bool fresh = b.dst != ops[i].src;
+            for (size_t k = i; k <= j; ++k) fresh = fresh && ops[k].dst != b.dst;
+            if (!fresh) break;
+            ++j;
+        }
+        return j > i ? pp.len_at(0, (int32_t)(j - i + 1)) : 1;
+    };
     // the opening chain of advances was run by dcp_revolve_forward
     size_t i0 = 0;
     while (i0 < ops.size() && ops[i0].kind == kRvAdvance) ++i0;
     for (size_t i = i0; i < ops.size(); ++i) {
         const RvOp &op = ops[i];
-        if (op.kind == kRvAdvance) {
+        if (op.kind == kRvAdvance && op.t1 - op.t0 == 1) {
+            const int len = chain(i);
+            if (len >= 2) {
+                DCP_TRY(fwd_pass(dtype, bc, g, c, t, pp, len, B.buf(op.src), f, B.buf(ops[i + len - 1].dst),
+                                 B.buf(op.dst), len == 3 ? B.buf(ops[i + 1].dst) : nullptr, st));
+                i += len - 1;
+                continue;
+            }
+        }
+        const bool folded = fold(i);
+        if (op.kind == kRvAdvance && !folded) {
             if ((rc = rev_advance(dtype, bc, g, c, t, pp, f, B.buf(op.src), B.buf(op.dst), scratch,
                                   op.t1 - op.t0, st)))
                 return rc;
             continue;
         }
-        const int64_t s = op.t0;  // adjoint step s with u_s in buffer op.src
-        void *out = (s == 0) ? grad_u0 : (lcur == lam[0] ? lam[1] : lam[0]);
-        aa.s = lcur;
-        aa.q = B.buf(op.src);
-        aa.out = out;
-        aa.partials = partials + (size_t)s * stride * 2;
-        aa.lam_first = lam_first;
-        DCP_TRY(launch_stencil(dtype, adj_op, bc, true, t, aa, st));
+        // adjoint step s with u_s in buffer src, or recomputed from u_{s-1};
+        // or steps s and s - 1 when the next operation is step s - 1
+        const RvOp &adj = folded ? ops[i + 1] : op;
+        const int64_t s = adj.t0;
+        const bool pair = !folded && use_tb && i + 1 < ops.size() && ops[i + 1].kind == kRvAdjoint &&
+                          ops[i + 1].t0 == s - 1;
+        const int64_t se = pair ? s - 1 : s;
+        void *out = (se == 0) ? grad_u0 : (lcur == lam[0] ? lam[1] : lam[0]);
+        if (pair) {
+            ta.u = lcur;
+            ta.f = B.buf(adj.src);
+            ta.g2 = B.buf(ops[i + 1].src);
+            ta.out = out;
+            ta.mid = nullptr;
+            ta.part1 = partials + (size_t)s * stride * 2;
+            ta.part2 = partials + (size_t)(s - 1) * stride * 2;
+            ta.lam_first = lam_first;
+            DCP_TRY(launch_tb2(dtype, adj_op, bc, true, tb, ta, st));
+            step_nblk[s] = step_nblk[s - 1] = tb.nblk;
+        } else {
+            aa.s = lcur;
+            aa.q = folded ? f : B.buf(adj.src);
+            aa.s2 = folded ? B.buf(op.src) : nullptr;
+            aa.out = out;
+            aa.partials = partials + (size_t)s * stride * 2;
+            aa.lam_first = lam_first;
+            DCP_TRY(launch_stencil(dtype, folded ? adj_rop : adj_op, bc, true, t, aa, st));
+        }
         lam_first = 0;
         lcur = out;
+        if (folded || pair) ++i;
     }
-    DCP_TRY(launch_finalize(partials, t.nblk, stride, T, sums, nullptr, 2, st));
+    // per-step sums in a fixed order, then over the steps in a fixed order
+    for (int32_t s0 = 0; s0 < T;) {
+        int32_t s1 = s0 + 1;
+        while (s1 < T && step_nblk[s1] == step_nblk[s0]) ++s1;
+        DCP_TRY(launch_finalize(partials + (size_t)s0 * stride * 2, step_nblk[s0], stride, s1 - s0,
+                                sums + 2 * (size_t)s0, nullptr, 2, st));
+        s0 = s1;
+    }
     DCP_TRY(launch_grad_finalize(sums, T, c.dt / (c.h * c.h), -c.dt, grad_ab, st));
     if (lsum) {
         if (grad_gamma) {

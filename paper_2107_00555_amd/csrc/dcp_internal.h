@@ -31,6 +31,11 @@ enum StencilOp : int {
     SOP_LAP = 2,  // lap = (((((xm+xp)+ym)+yp)+zm)+zp - 6u) / c0, one rounding per op
     SOP_ADJL = 3, // SOP_ADJ, and lam += l (the adjoint step's input, lambda_{t+1});
                   // lam_first: lam = l + 0 without reading lam
+    SOP_ADJR = 4, // SOP_ADJ with u = u_t recomputed at each point from u_{t-1}
+                  // (operand s2, stenciled) and f (operand q) by SOP_FWD's
+                  // arithmetic with c0, c1f, c2f: one forward step and one
+                  // adjoint step in one pass
+    SOP_ADJLR = 5,  // SOP_ADJR, and lam += l as in SOP_ADJL
 };
 
 // Tile of one workgroup: 64*bxw*vec points along x (bxw waves side by side),
@@ -48,9 +53,11 @@ struct StencilArgs {
     const void *q;       // point operand (f, or u_t); unused by SOP_LAP
     void *out;           // output field
     double *partials;    // [nblk][2] per-workgroup sums, or null
-    void *lam;           // SOP_ADJL: running sum of the adjoint inputs
+    void *lam;           // SOP_ADJL, SOP_ADJLR: running sum of the adjoint inputs
+    const void *s2;      // SOP_ADJR, SOP_ADJLR: u_{t-1} (stencil operand of the recomputation)
     int64_t nx, ny, nz;
     double c0, c1, c2;
+    double c1f, c2f;     // SOP_ADJR, SOP_ADJLR: the forward step's c1 and c2
     int tiles_x, tiles_y, zc, nblk;
     int lam_first;
 };

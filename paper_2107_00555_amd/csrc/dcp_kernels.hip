@@ -146,7 +146,10 @@ __global__ void __launch_bounds__(64 * BXW * BY) stencil_kernel(StencilArgs a) {
     const int64_t z0 = (int64_t)tz * a.zc;
     const int64_t z1 = min(nz, z0 + (int64_t)a.zc);
 
+    constexpr bool RECOMP = OP == SOP_ADJR || OP == SOP_ADJLR;  // u_t recomputed from u_{t-1}
+    constexpr bool LSUM = OP == SOP_ADJL || OP == SOP_ADJLR;    // lam += lambda_{t+1}
     const T *__restrict__ S = static_cast<const T *>(a.s);
+    const T *__restrict__ V = static_cast<const T *>(a.s2);
     const T *__restrict__ Q = static_cast<const T *>(a.q);
     T *__restrict__ O = static_cast<T *>(a.out);
 
@@ -158,17 +161,20 @@ __global__ void __launch_bounds__(64 * BXW * BY) stencil_kernel(StencilArgs a) {
     const int64_t xr = wrap<BC>(x0 + VEC, nx);
 
     const T C0 = (T)a.c0, C1 = (T)a.c1, C2 = (T)a.c2;
+    const T C1F = (T)a.c1f, C2F = (T)a.c2f;
 
-    // loaders for a resolved plane index zr (-1 = ghost plane)
-    auto load_rows = [&](int64_t zr, T (&d)[RY][VEC]) {
+    // loaders for a resolved plane index zr (-1 = ghost plane) of a stencil
+    // operand P (S, or V)
+    auto load_rows_of = [&](const T *P, int64_t zr, T (&d)[RY][VEC]) {
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             if (active && zr >= 0 && r < nrow)
-                load_vec<T, VEC>(d[r], S + zr * sz + (yf + r) * sy + x0);
+                load_vec<T, VEC>(d[r], P + zr * sz + (yf + r) * sy + x0);
             else
                 zero_vec<T, VEC>(d[r]);
         }
     };
+    auto load_rows = [&](int64_t zr, T (&d)[RY][VEC]) { load_rows_of(S, zr, d); };
     auto load_point = [&](int64_t z, T (&d)[RY][VEC]) {
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
@@ -178,24 +184,30 @@ __global__ void __launch_bounds__(64 * BXW * BY) stencil_kernel(StencilArgs a) {
                 zero_vec<T, VEC>(d[r]);
         }
     };
-    auto load_halo = [&](int64_t z, T (&ht)[VEC], T (&hb)[VEC], T (&el)[RY], T (&er)[RY]) {
+    auto load_halo_of = [&](const T *P, int64_t z, T (&ht)[VEC], T (&hb)[VEC], T (&el)[RY], T (&er)[RY]) {
         if (active && ytop >= 0)
-            load_vec<T, VEC>(ht, S + z * sz + ytop * sy + x0);
+            load_vec<T, VEC>(ht, P + z * sz + ytop * sy + x0);
         else
             zero_vec<T, VEC>(ht);
         if (active && ybot >= 0)
-            load_vec<T, VEC>(hb, S + z * sz + ybot * sy + x0);
+            load_vec<T, VEC>(hb, P + z * sz + ybot * sy + x0);
         else
             zero_vec<T, VEC>(hb);
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-            el[r] = (need_l && xl >= 0 && r < nrow) ? S[z * sz + (yf + r) * sy + xl] : T(0);
-            er[r] = (need_r && xr >= 0 && r < nrow) ? S[z * sz + (yf + r) * sy + xr] : T(0);
+            el[r] = (need_l && xl >= 0 && r < nrow) ? P[z * sz + (yf + r) * sy + xl] : T(0);
+            er[r] = (need_r && xr >= 0 && r < nrow) ? P[z * sz + (yf + r) * sy + xr] : T(0);
         }
+    };
+    auto load_halo = [&](int64_t z, T (&ht)[VEC], T (&hb)[VEC], T (&el)[RY], T (&er)[RY]) {
+        load_halo_of(S, z, ht, hb, el, er);
     };
 
     T um[RY][VEC], uc[RY][VEC], up[RY][VEC], qc[RY][VEC];
     T ht[VEC], hb[VEC], el[RY], er[RY];
+    // the recomputation's stencil operand u_{t-1} (RECOMP only; otherwise unused)
+    T vm[RY][VEC], vc[RY][VEC], vp[RY][VEC];
+    T vht[VEC], vhb[VEC], vel[RY], ver[RY];
     double acc0 = 0.0, acc1 = 0.0;
 
     if (z0 < z1) {
@@ -204,25 +216,42 @@ __global__ void __launch_bounds__(64 * BXW * BY) stencil_kernel(StencilArgs a) {
         load_halo(z0, ht, hb, el, er);
         if constexpr (OP != SOP_LAP) load_point(z0, qc);
         load_rows(wrap<BC>(z0 + 1, nz), up);
+        if constexpr (RECOMP) {
+            load_rows_of(V, wrap<BC>(z0 - 1, nz), vm);
+            load_rows_of(V, z0, vc);
+            load_halo_of(V, z0, vht, vhb, vel, ver);
+            load_rows_of(V, wrap<BC>(z0 + 1, nz), vp);
+        }
     }
 
     for (int64_t z = z0; z < z1; ++z) {
         T un[RY][VEC], qn[RY][VEC], htn[VEC], hbn[VEC], eln[RY], ern[RY];
+        T vn[RY][VEC], vhtn[VEC], vhbn[VEC], veln[RY], vern[RY];
         const bool more = z + 1 < z1;
         if (more) {
             load_rows(wrap<BC>(z + 2, nz), un);
             if constexpr (OP != SOP_LAP) load_point(z + 1, qn);
             load_halo(z + 1, htn, hbn, eln, ern);
+            if constexpr (RECOMP) {
+                load_rows_of(V, wrap<BC>(z + 2, nz), vn);
+                load_halo_of(V, z + 1, vhtn, vhbn, veln, vern);
+            }
         }
 
         // x-neighbours of each row's first and last element
-        T lft[RY], rgt[RY];
+        T lft[RY], rgt[RY], vlft[RY], vrgt[RY];
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             lft[r] = __shfl_up(uc[r][VEC - 1], 1, 64);
             rgt[r] = __shfl_down(uc[r][0], 1, 64);
             if (need_l) lft[r] = el[r];
             if (need_r) rgt[r] = er[r];
+            if constexpr (RECOMP) {
+                vlft[r] = __shfl_up(vc[r][VEC - 1], 1, 64);
+                vrgt[r] = __shfl_down(vc[r][0], 1, 64);
+                if (need_l) vlft[r] = vel[r];
+                if (need_r) vrgt[r] = ver[r];
+            }
         }
 
         if (active) {
@@ -249,7 +278,21 @@ __global__ void __launch_bounds__(64 * BXW * BY) stencil_kernel(StencilArgs a) {
                         } else {
                             const T s6 = ((xm + xp) + (ym + yp)) + (zm + zp);
                             const T lapn = fma(T(-6), c, s6);  // h^2 * Lap7 at this point
-                            const T qv = qc[r][e];
+                            T qv = qc[r][e];
+                            if constexpr (RECOMP) {
+                                // u_t = u_{t-1} + c0*(S6 - 6u) - c1f*u^3 + c2f*f, as SOP_FWD
+                                const T v = vc[r][e];
+                                const T vxm = e == 0 ? vlft[r] : vc[r][e > 0 ? e - 1 : 0];
+                                const T vxp = e == VEC - 1 ? vrgt[r] : vc[r][e + 1 < VEC ? e + 1 : e];
+                                const T vym = r == 0 ? vht[e] : vc[r > 0 ? r - 1 : 0][e];
+                                const T vyp = (r == nrow - 1) ? vhb[e] : vc[r + 1 < RY ? r + 1 : r][e];
+                                const T vs6 = ((vxm + vxp) + (vym + vyp)) + (vm[r][e] + vp[r][e]);
+                                const T vlap = fma(T(-6), v, vs6);
+                                T ut = fma(C2F, qv, v);
+                                ut = fma(C0, vlap, ut);
+                                ut = fma(-(C1F * v) * v, v, ut);
+                                qv = ut;
+                            }
                             if constexpr (OP == SOP_FWD) {
                                 T acc = fma(C2, qv, c);
                                 acc = fma(C0, lapn, acc);
@@ -261,7 +304,7 @@ __global__ void __launch_bounds__(64 * BXW * BY) stencil_kernel(StencilArgs a) {
                                     const double dd = d - (double)c;
                                     acc1 = fma(dd, dd, acc1);
                                 }
-                            } else {  // SOP_ADJ: c = lambda_{t+1}, qv = u_t
+                            } else {  // the adjoint ops: c = lambda_{t+1}, qv = u_t
                                 T acc = fma(C0, lapn, c);
                                 acc = fma(-(C1 * qv) * qv, c, acc);
                                 res[e] = acc;
@@ -274,7 +317,7 @@ __global__ void __launch_bounds__(64 * BXW * BY) stencil_kernel(StencilArgs a) {
                         }
                     }
                     store_vec_nt<T, VEC>(O + z * sz + (yf + r) * sy + x0, res);
-                    if constexpr (OP == SOP_ADJL) {
+                    if constexpr (LSUM) {
                         // running sum of the adjoint inputs: lam += lambda_{t+1}
                         T *lp = static_cast<T *>(a.lam) + z * sz + (yf + r) * sy + x0;
                         T lv[VEC];
@@ -297,14 +340,27 @@ __global__ void __launch_bounds__(64 * BXW * BY) stencil_kernel(StencilArgs a) {
                     uc[r][e] = up[r][e];
                     up[r][e] = un[r][e];
                     if constexpr (OP != SOP_LAP) qc[r][e] = qn[r][e];
+                    if constexpr (RECOMP) {
+                        vm[r][e] = vc[r][e];
+                        vc[r][e] = vp[r][e];
+                        vp[r][e] = vn[r][e];
+                    }
                 }
                 el[r] = eln[r];
                 er[r] = ern[r];
+                if constexpr (RECOMP) {
+                    vel[r] = veln[r];
+                    ver[r] = vern[r];
+                }
             }
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
                 ht[e] = htn[e];
                 hb[e] = hbn[e];
+                if constexpr (RECOMP) {
+                    vht[e] = vhtn[e];
+                    vhb[e] = vhbn[e];
+                }
             }
         }
     }
@@ -358,6 +414,10 @@ hipError_t launch_shape(int op, int bc, bool reduce, int nblk, const StencilArgs
             DCP_L(0, SOP_ADJ, true);
         } else if (op == SOP_ADJL) {
             DCP_L(0, SOP_ADJL, true);
+        } else if (op == SOP_ADJR) {
+            DCP_L(0, SOP_ADJR, true);
+        } else if (op == SOP_ADJLR) {
+            DCP_L(0, SOP_ADJLR, true);
         } else {
             DCP_L(0, SOP_LAP, false);
         }
@@ -369,6 +429,10 @@ hipError_t launch_shape(int op, int bc, bool reduce, int nblk, const StencilArgs
             DCP_L(1, SOP_ADJ, true);
         } else if (op == SOP_ADJL) {
             DCP_L(1, SOP_ADJL, true);
+        } else if (op == SOP_ADJR) {
+            DCP_L(1, SOP_ADJR, true);
+        } else if (op == SOP_ADJLR) {
+            DCP_L(1, SOP_ADJLR, true);
         } else {
             DCP_L(1, SOP_LAP, false);
         }
