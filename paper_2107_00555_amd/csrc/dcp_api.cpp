@@ -379,9 +379,12 @@ struct PassPlan {
     bool use_tb = false, use_k2 = false, use_k3 = false;
     TbTile tb{};
     TbkTile k2{}, k3{};
+    // steps in the pass starting at step s of T: three where possible, but
+    // four steps left go as two passes of two (cheaper than three and one)
     int32_t len_at(int32_t s, int32_t T) const {
-        if (use_k3 && s + 3 <= T) return 3;
-        if ((use_tb || use_k2) && s + 2 <= T) return 2;
+        const bool two = use_tb || use_k2;
+        if (use_k3 && s + 3 <= T && !(two && T - s == 4)) return 3;
+        if (two && s + 2 <= T) return 2;
         return 1;
     }
 };
@@ -548,15 +551,13 @@ struct RevBufs {
 
 // n fused steps from `from` into `to` (n >= 1; both distinct from the
 // scratch field), in the passes of `pp` (up to three steps each where the
-// grid allows it; four steps left go as two passes of two, which cost less
-// than three and one), alternating between `to` and the scratch so the last
-// pass lands in `to`.
+// grid allows it), alternating between `to` and the scratch so the last pass
+// lands in `to`.
 int rev_advance(int dtype, int bc, const Geo &g, const dcp_coeffs &c, const Tile &t, const PassPlan &pp,
                 const void *f, const void *from, void *to, void *scratch, int64_t n, hipStream_t st) {
     std::vector<int> lens;
     for (int64_t left = n; left > 0;) {
-        int k = pp.len_at(0, left > 3 ? 3 : (int32_t)left);
-        if (left == 4 && k == 3 && pp.len_at(0, 2) == 2) k = 2;
+        const int k = pp.len_at(0, left > 4 ? 4 : (int32_t)left);
         lens.push_back(k);
         left -= k;
     }
@@ -936,7 +937,7 @@ int dcp_adjoint_run(int dtype, const void *ckpt, int32_t ckpt_every, const void 
         const void *prev = slot(cs);
         for (int32_t j = 1; j < t1 - t0;) {
             const int32_t left = t1 - t0 - j;
-            const int len = fpp.len_at(0, left > 3 ? 3 : left);
+            const int len = fpp.len_at(0, left > 4 ? 4 : left);
             DCP_TRY(fwd_pass(dtype, bc, g, c, t, fpp, len, prev, f, seg(j + len - 2),
                              len >= 2 ? seg(j - 1) : nullptr, len == 3 ? seg(j) : nullptr, st));
             prev = seg(j + len - 2);

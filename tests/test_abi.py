@@ -309,12 +309,15 @@ def test_revolve_argument_errors(L, host_only):
 def test_run_plan_reports_the_passes(L, monkeypatch):
     # which passes dcp_run takes (host-side plan; 160 KiB of LDS without a GPU)
     monkeypatch.delenv("DCP_TBK_CFG", raising=False)
+    # three steps per pass; the last four steps as two passes of two
     p = L.run_plan(L.F64, 512, 512, 512, 100, 3)
-    assert p["passes"] == [1, 0, 33] and p["steps_per_pass"] == 3
+    assert p["passes"] == [0, 2, 32] and p["steps_per_pass"] == 3
     p = L.run_plan(L.F64, 512, 512, 512, 100, 2)
     assert p["passes"] == [0, 50, 0] and p["steps_per_pass"] == 2 and p["segmented"] == 0
     p = L.run_plan(L.F32, 512, 512, 512, 100, 3)
-    assert p["passes"] == [1, 0, 33]
+    assert p["passes"] == [0, 2, 32]
+    assert L.run_plan(L.F64, 512, 512, 512, 99, 3)["passes"] == [0, 0, 33]
+    assert L.run_plan(L.F64, 512, 512, 512, 98, 3)["passes"] == [0, 1, 32]
     p = L.run_plan(L.F64, 512, 512, 512, 100, 1)
     assert p["passes"] == [100, 0, 0] and p["steps_per_pass"] == 1
     p = L.run_plan(L.F64, 512, 512, 512, 7, 1, impl=L.UNFUSED)
