@@ -609,14 +609,21 @@ __global__ void __launch_bounds__(64) j2m_kernel(J2MArgs a) {
                 for (int k = 0; k < CPL; ++k) S[s][mid][k] = nv[k];
             }
             // A's row r is in the segment on the plain path; B's row (the
-            // level before) is stored by the last pass only
+            // level before) is stored by the last pass only.  With two
+            // columns per lane a store covers whole lines and goes out with
+            // the streaming hint; with four, the lane's two stores fill each
+            // line in halves, which L2 merges when the stores are ordinary
+            // (streamed halves reach HBM as separate partial writes: 1.23x
+            // the written bytes, measured)
             if (s == NH && (!general || (r >= R0 && r < R1))) {
                 const int64_t ro = (int64_t)r * n1 + gc;
 #pragma unroll
-                for (int p = 0; p < NP; ++p)
-                    if (ownp[p])
-                        __builtin_nontemporal_store(j2m_v2{nv[2 * p], nv[2 * p + 1]},
-                                                    reinterpret_cast<j2m_v2 *>(a.aout + ro + 2 * p));
+                for (int p = 0; p < NP; ++p) {
+                    if (!ownp[p]) continue;
+                    j2m_v2 *dst = reinterpret_cast<j2m_v2 *>(a.aout + ro + 2 * p);
+                    if constexpr (CPL == 2) __builtin_nontemporal_store(j2m_v2{nv[2 * p], nv[2 * p + 1]}, dst);
+                    else *dst = j2m_v2{nv[2 * p], nv[2 * p + 1]};
+                }
             }
             if (s == NH - 1 && a.write_b != 0 && r >= R0 && r < R1) {
                 const int64_t ro = (int64_t)r * n1 + gc;
