@@ -557,7 +557,7 @@ int rev_advance(int dtype, int bc, const Geo &g, const dcp_coeffs &c, const Tile
                 const void *f, const void *from, void *to, void *scratch, int64_t n, hipStream_t st) {
     std::vector<int> lens;
     for (int64_t left = n; left > 0;) {
-        const int k = pp.len_at(0, left > 4 ? 4 : (int32_t)left);
+        const int k = pp.len_at(0, (int32_t)std::min<int64_t>(left, INT32_MAX));
         lens.push_back(k);
         left -= k;
     }
@@ -937,7 +937,7 @@ int dcp_adjoint_run(int dtype, const void *ckpt, int32_t ckpt_every, const void 
         const void *prev = slot(cs);
         for (int32_t j = 1; j < t1 - t0;) {
             const int32_t left = t1 - t0 - j;
-            const int len = fpp.len_at(0, left > 4 ? 4 : left);
+            const int len = fpp.len_at(0, left);
             DCP_TRY(fwd_pass(dtype, bc, g, c, t, fpp, len, prev, f, seg(j + len - 2),
                              len >= 2 ? seg(j - 1) : nullptr, len == 3 ? seg(j) : nullptr, st));
             prev = seg(j + len - 2);
