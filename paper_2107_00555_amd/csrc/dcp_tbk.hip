@@ -518,7 +518,7 @@ bool tbk_plan(int dtype, int B, int64_t nx, int64_t ny, int64_t nz, bool vec_ok,
                 // make that run a block of slabs across all segments, so the
                 // halo rows and chunks a tile shares with its neighbours are
                 // read through the same L2 (measured at 512^3 FP64: reads per
-                // pass 2.55 -> 2.12 GiB, 1.06x the algorithmic 2 GiB)
+                // pass 2.55 -> 2.28 GiB, 1.14x the algorithmic 2 GiB)
                 int64_t per = (t->nblk + 7) / 8 / nseg;
                 t->sblk = (int)(per < 1 ? 1 : per > nslab ? nslab : per);
             }

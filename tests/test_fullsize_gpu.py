@@ -100,6 +100,13 @@ def test_fwd_512_f32_streaming_per_step(fields_512, oracle_512_f64, request):
     assert torch.equal(up, u)
     assert np.array_equal(to_host(op["energy"]), e_gpu) and np.array_equal(to_host(op["resid"]), r_gpu)
     del up, op
+    say("512^3 f32: plain run with three steps per pass (the benchmark's default)")
+    u3 = to_dev(u0, torch.float32)
+    o3 = api.run(u3, fd, C, 100, bc, impl="fused", tblock=3, norms=True)
+    torch.cuda.synchronize()
+    assert torch.equal(u3, u)
+    e3, r3 = to_host(o3["energy"]), to_host(o3["resid"])
+    del u3, o3
     assert torch.equal(ck[0], to_dev(u0, torch.float32))
 
     field_err = np.zeros(100)
@@ -121,6 +128,10 @@ def test_fwd_512_f32_streaming_per_step(fields_512, oracle_512_f64, request):
     oracle.run_stream(u0, f, C, 100, bc, observe_norms)
     e_err = np.abs(e_gpu - e_or) / e_or
     r_err = np.abs(r_gpu - r_or) / r_or
+    e3_err = np.abs(e3 - e_or) / e_or
+    r3_err = np.abs(r3 - r_or) / r_or
+    progress(cfg, f"512^3 f32 three steps per pass: E_t <= {e3_err.max():.2e}, R_t <= {r3_err.max():.2e}")
+    assert e3_err.max() <= 1e-5 and r3_err.max() <= 1e-5
     print("f32 per-step normwise field error vs FP64 oracle:", np.array2string(field_err, precision=2))
     print("f32 per-step E_t relative error:", np.array2string(e_err, precision=2))
     print("f32 per-step R_t relative error:", np.array2string(r_err, precision=2))
@@ -132,7 +143,7 @@ def test_fwd_512_f32_streaming_per_step(fields_512, oracle_512_f64, request):
 
 
 @pytest.mark.timeout(1200)
-@pytest.mark.parametrize("impl,tblock", [("fused", 2), ("fused", 1), ("unfused", 1)])
+@pytest.mark.parametrize("impl,tblock", [("fused", 3), ("fused", 2), ("fused", 1), ("unfused", 1)])
 def test_fwd_512_f64_full_field(fields_512, oracle_512_f64, request, impl, tblock):
     # Headline workload, whole grid: u_100 and every E_t, R_t against the
     # oracle (the unfused chain rounds each statement as the oracle does:
