@@ -51,7 +51,7 @@ COUNTERS = {1: os.path.join(ROOT, "profiles", "stencil_fused_f64_512_counters.md
             3: os.path.join(ROOT, "profiles", "tbk3_fused_f64_512_counters.md")}
 KERNEL_NAMES = {1: "stencil_kernel<double,2,1,4,4,PERIODIC,FWD,norms> (one step per launch)",
                 2: "tb2_kernel<double,2,4,1024,2,PERIODIC,FWD,norms> (two steps per launch)",
-                3: "tbk_kernel<double,2,3,1024,2,PERIODIC,segments,norms> (three steps per launch)"}
+                3: "tbr_kernel<double,2,3,768,2,PERIODIC,segments,norms> (three steps per launch, register rings)"}
 
 
 def parse():

@@ -154,23 +154,28 @@ struct RunWs {
 // LDS of one workgroup on gfx950, the most a two-step pass may plan for.
 constexpr size_t kLdsMax = 160 * 1024;
 
-// Plan of a B-step pass (dcp_tbk.hip).  DCP_TBK_CFG="wc,ty,lanes" restricts
-// the planner to segments of wc chunks (a value covering the row: whole
-// rows), slabs of ty rows and 1024 or 512 lanes; 0 leaves a choice to the
+// Plan of a B-step pass (dcp_tbk.hip): the ring form (768 lanes) where a
+// tile fits it, else 1024 lanes.  DCP_TBK_CFG="wc,ty,lanes" restricts the
+// planner to segments of wc chunks (a value covering the row: whole rows),
+// slabs of ty rows and 768, 1024 or 512 lanes; 0 leaves a choice to the
 // planner.  DCP_TBK_SBLK sets the slabs per block of the tile order.
 // Tuning overrides only: every choice computes the same states bit for bit
 // (the norms' summation order follows the tiles).
 bool tbk_for(int dtype, const Geo &g, int B, bool vok, size_t lds_limit, TbkTile *t) {
-    int wc = 0, ty = 0, lanes = 1024;
+    int wc = 0, ty = 0, lanes = 0;
     if (const char *e = tuning_env("DCP_TBK_CFG")) {
         int a = 0, b = 0, c = 0;
         if (std::sscanf(e, "%d,%d,%d", &a, &b, &c) == 3) {
             wc = a > 0 ? a : 0;
             ty = b > 0 ? b : 0;
-            lanes = c == 512 ? 512 : 1024;
+            lanes = c == 512 || c == 768 || c == 1024 ? c : 0;
         }
     }
-    if (!tbk_plan(dtype, B, g.nx, g.ny, g.nz, vok, lds_limit, lanes, wc, ty, t)) return false;
+    bool ok = false;
+    if (lanes) ok = tbk_plan(dtype, B, g.nx, g.ny, g.nz, vok, lds_limit, lanes, wc, ty, t);
+    else ok = tbk_plan(dtype, B, g.nx, g.ny, g.nz, vok, lds_limit, 768, wc, ty, t) ||
+              tbk_plan(dtype, B, g.nx, g.ny, g.nz, vok, lds_limit, 1024, wc, ty, t);
+    if (!ok) return false;
     if (const char *e = tuning_env("DCP_TBK_SBLK")) {
         const int h = std::atoi(e);
         if (h > 0) t->sblk = h < t->nslab ? h : t->nslab;

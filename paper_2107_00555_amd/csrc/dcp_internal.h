@@ -154,7 +154,8 @@ struct TbkTile {
     size_t lds_bytes;
 };
 // Plans a B-step pass; false if the kernel does not apply (no 16-byte lanes,
-// or no tile fits the LDS).  lanes: 1024 or 512 lanes per workgroup.  When
+// or no tile fits the LDS).  lanes: 768 (the ring form, planes under 4
+// GiB), 1024 or 512 lanes per workgroup.  When
 // force_wc > 0 only segments of that many chunks (or whole rows, if it
 // covers the row) are considered; force_ty > 0 fixes the slab height.
 bool tbk_plan(int dtype, int B, int64_t nx, int64_t ny, int64_t nz, bool vec_ok, size_t lds_limit, int lanes,

@@ -27,6 +27,9 @@
 //     lane's registers (register queues);
 //   * at iteration q, stage s computes level s at plane q-s+1 (a B-stage
 //     z-pipeline), two barriers per plane.
+// The ring form (tbr_kernel, 768 lanes, the planner's first choice) keeps
+// all z-neighbours in registers and needs one barrier per plane; the form
+// above serves the tiles that only fit 1024 or 512 lanes.
 // Every point is computed with the same operations, in the same order, as
 // the one-step kernel, so a pass equals B one-step launches bit for bit.
 // The norms of all B steps are reduced over the owned points only.
@@ -408,13 +411,322 @@ __global__ void __launch_bounds__(NT) tbk_kernel(TbkArgs a) {
     }
 }
 
-template <typename T, int VEC, int B, int NT, int KM>
+// Ring form of the same pass, for shapes with up to 168 (768 lanes) or 256
+// (512 lanes) VGPRs.  Each lane keeps, for its own chunks, the three planes
+// of every level that the next level reads (p-1, p, p+1) in registers, so
+// only the y- and x-neighbours of a point come from LDS:
+//   * level 0 (u) in a ring of three planes, the load of plane q+2 issued as
+//     soon as plane q-1 is dead (after stage 1 of iteration q);
+//   * level s (1 .. B-1) in a ring of three planes, written by stage s and
+//     read by stage s+1 of the same and the next two iterations;
+//   * f in a ring of three planes loaded two planes ahead; with B = 3 the
+//     plane the last stage needs waits in one LDS plane of the lane's own
+//     chunks;
+//   * level 0 in two LDS planes (the current plane and the next), so one
+//     barrier per plane separates every LDS write from the reads of it and
+//     every read from the next write to the same buffer.
+// Ring slots are (plane - q0) mod 3, compile-time constants in a plane loop
+// unrolled three times, so no register copies rotate the queues.  Every
+// point is computed with the one-step kernel's operations, as in tbk_kernel.
+template <typename T, int VEC, int B, int NT, int KM, int BC, bool SEG, bool RED>
+__global__ void __launch_bounds__(NT) tbr_kernel(TbkArgs a) {
+    static_assert(B >= 2 && B <= 3, "two or three steps per pass");
+    extern __shared__ __align__(16) unsigned char tbk_smem[];
+    const int nx = (int)a.nx, ny = (int)a.ny, nz = (int)a.nz;
+    const int64_t sz = a.nx * a.ny;
+    const int TY = a.ty;
+    const int CHF = a.chf;
+    const int FW = CHF * VEC;
+    const int CH = nx / VEC;
+    const int R0 = TY + 2 * B;
+    T *const SM = reinterpret_cast<T *>(tbk_smem);
+    // LDS: level 0 at planes of both parities (R0 rows each), then level s =
+    // 1 .. B-1 at both parities (frame rows s .. R0-s-1), then (B = 3) f on
+    // the level-1 rows; every buffer is addressed with a chunk's level-0
+    // frame offset (bases shifted back by the buffer's first row).
+    auto L0p = [&](int p) -> T * { return SM + (p & 1) * R0 * FW; };
+    auto LSp = [&](int s, int p) -> T * {
+        const int off = s == 1 ? 2 * R0 : 4 * R0 - 4;
+        return SM + (off + (p & 1) * (R0 - 2 * s) - s) * FW;
+    };
+    T *const FB = SM + (6 * R0 - 12 - 1) * FW;
+
+    const int tid = threadIdx.x;
+    const int wlane = tid & 63;
+    const int Lb = k_xcd_remap(blockIdx.x, gridDim.x);
+    const int ncol = a.nslab * a.nseg;
+    const int cb = Lb % ncol;
+    const int zrun = Lb / ncol;
+    const int blk = cb / (a.nseg * a.sblk);
+    const int rem = cb - blk * a.nseg * a.sblk;
+    const int hb = min(a.sblk, a.nslab - blk * a.sblk);
+    const int seg = rem / hb;
+    const int slab = blk * a.sblk + rem % hb;
+    const int y0 = slab * TY;
+    const int z0 = zrun * a.zc;
+    const int z1 = min(nz, z0 + a.zc);
+    const int gc0 = SEG ? seg * a.wc - a.halo : 0;
+    const int oc0 = SEG ? a.halo : 0;
+    const int oc1 = SEG ? a.halo + min(a.wc, CH - seg * a.wc) : CH;
+
+    const T *__restrict__ U = static_cast<const T *>(a.u);
+    const T *__restrict__ F = static_cast<const T *>(a.f);
+    T *__restrict__ O = static_cast<T *>(a.out);
+    const T C0 = (T)a.c0, C1 = (T)a.c1, C2 = (T)a.c2;
+
+    int lofs[KM], gofs[KM];
+    unsigned flags[KM];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+        const int idx = tid + k * NT;
+        const bool v = idx < R0 * CHF;
+        const int r = v ? idx / CHF : 0;
+        const int c = v ? idx % CHF : 0;
+        const int gy = y0 - B + r;
+        const int gyr = k_wrap<BC>(gy, ny);
+        const int gcr = SEG ? k_wrap<BC>(gc0 + c, CH) : c;
+        lofs[k] = r * FW + c * VEC;
+        gofs[k] = (gyr >= 0 && gcr >= 0) ? gyr * nx + gcr * VEC : -1;
+        unsigned fl = (v ? kValid : 0u) | ((unsigned)c << kColShift);
+#pragma unroll
+        for (int s = 1; s <= B; ++s)
+            if (v && r >= s && r < R0 - s) fl |= 1u << s;
+        if (v && r >= B && r < B + TY && gy < ny && c >= oc0 && c < oc1) fl |= kOwned;
+        if (gofs[k] < 0) fl |= kGhost;
+        flags[k] = fl;
+    }
+
+    // Every lane loads, from a uniform plane base plus its chunk's 32-bit
+    // byte offset in the plane (the planner keeps a plane under 4 GiB for
+    // this kernel), so the ring registers have one writer and the loads'
+    // waits can be counted instead of drained.  Chunks outside the grid
+    // (ghost rows, columns or planes) and lanes past the frame read a valid
+    // chunk instead; level 0 of a ghost point is zeroed once, when its plane
+    // becomes a lane's upper z-neighbour, so its LDS copy and the x-exchange
+    // see zeros, and every higher level of a ghost point is computed as
+    // zero; f at a ghost point is never used.
+    uint32_t gb[KM];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) gb[k] = gofs[k] >= 0 ? (uint32_t)gofs[k] * (uint32_t)sizeof(T) : 0u;
+    auto at = [&](const T *plane, int k) -> const T * {
+        return reinterpret_cast<const T *>(reinterpret_cast<const char *>(plane) + gb[k]);
+    };
+    auto load_u = [&](int zq, T (&d)[KM][VEC]) {
+        const int zr = k_wrap<BC>(zq, nz);
+        const T *plane = U + (int64_t)(zr >= 0 ? zr : 0) * sz;
+#pragma unroll
+        for (int k = 0; k < KM; ++k) k_load<T, VEC>(d[k], at(plane, k));
+    };
+    auto load_f = [&](int zq, T (&d)[KM][VEC]) {
+        const int zr = k_wrap<BC>(zq, nz);
+        const T *plane = F + (int64_t)(zr >= 0 ? zr : 0) * sz;
+#pragma unroll
+        for (int k = 0; k < KM; ++k) k_load_nt<T, VEC>(d[k], at(plane, k));
+    };
+    // Dirichlet: level 0 at plane zq is zero on ghost chunks and planes
+    auto ghost0 = [&](int zq, T (&d)[KM][VEC]) {
+        if constexpr (BC == 0) {
+            const bool gp = zq < 0 || zq >= nz;
+#pragma unroll
+            for (int k = 0; k < KM; ++k) {
+                const bool g = gp || (flags[k] & kGhost);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) d[k][e] = g ? T(0) : d[k][e];
+            }
+        }
+    };
+    auto xnbrs = [&](const T *base, int o, int c, const T (&v)[VEC], T &lft, T &rgt) {
+        const T fl = k_dpp<0x138>(v[VEC - 1]);
+        const T fu = k_dpp<0x130>(v[0]);
+        if (c > 0) lft = wlane != 0 ? fl : base[o - 1];
+        else if (!SEG && BC == 1) lft = base[o + FW - 1];
+        else lft = T(0);
+        if (c < CHF - 1) rgt = wlane != 63 ? fu : base[o + VEC];
+        else if (!SEG && BC == 1) rgt = base[o - c * VEC];
+        else rgt = T(0);
+    };
+
+    // rings: slot (plane - q0) mod 3
+    T RU[3][KM][VEC];          // level 0
+    T RZ[B - 1][3][KM][VEC];   // levels 1 .. B-1
+    T RF[3][KM][VEC];          // f
+    double es[B], rs[B];
+#pragma unroll
+    for (int s = 0; s < B; ++s) es[s] = rs[s] = 0.0;
+
+    const int q0 = z0 - B + 1;
+    const int qlast = z1 + B - 2;
+    // plane q0 + j sits in slot j mod 3; at iteration q (phase ph = (q -
+    // q0) mod 3) plane q + d sits in slot rs3(ph + d)
+    constexpr auto rs3 = [](int v) constexpr { return ((v % 3) + 3) % 3; };
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+#pragma unroll
+        for (int s = 0; s < B - 1; ++s)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) k_zero<T, VEC>(RZ[s][j][k]);
+        k_zero<T, VEC>(RF[2][k]);
+    }
+    if (z0 < z1) {
+        load_u(q0 - 1, RU[2]);
+        load_u(q0, RU[0]);
+        load_u(q0 + 1, RU[1]);
+        load_f(q0, RF[0]);
+        load_f(q0 + 1, RF[1]);
+        ghost0(q0 - 1, RU[2]);
+        ghost0(q0, RU[0]);
+#pragma unroll
+        for (int k = 0; k < KM; ++k)
+            if (flags[k] & kValid) k_store<T, VEC>(L0p(q0) + lofs[k], RU[0][k]);
+    }
+    // the prologue's loads have landed: the loop starts with no load in
+    // flight on the path from here, so its waits count only its own loads
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+
+    auto iter = [&](auto phc, const int q) {
+        constexpr int PH = decltype(phc)::value;
+        ghost0(q + 1, RU[rs3(PH + 1)]);
+#pragma unroll
+        for (int s = 1; s <= B; ++s) {
+            if (q < q0 + 2 * (s - 1)) continue;  // stage s starts two planes after stage s-1
+            const int p = q - s + 1;               // plane of level s
+            const bool owned_plane = p >= z0 && p < z1;
+            const int pr = k_wrap<BC>(p, nz);
+            const T *src = s == 1 ? L0p(q) : LSp(s - 1, p);
+            T *dst = s < B ? LSp(s, p) : nullptr;
+            T *mid = s < B ? static_cast<T *>(a.mid[s - 1]) : nullptr;
+            // level s-1 at planes p-1, p, p+1 (registers), level s at p (result)
+            T(&Lm)[KM][VEC] = s == 1 ? RU[rs3(PH - 1)] : RZ[s >= 2 ? s - 2 : 0][rs3(PH - s)];
+            T(&Lc)[KM][VEC] = s == 1 ? RU[rs3(PH)] : RZ[s >= 2 ? s - 2 : 0][rs3(PH + 1 - s)];
+            T(&Lp)[KM][VEC] = s == 1 ? RU[rs3(PH + 1)] : RZ[s >= 2 ? s - 2 : 0][rs3(PH + 2 - s)];
+            T(&Lo)[KM][VEC] = RZ[s < B ? s - 1 : 0][rs3(PH + 1 - s)];
+            // the y- and x-neighbours in the frame plane come from LDS, the
+            // z-neighbours and the centre from the rings
+#pragma unroll
+            for (int k = 0; k < KM; ++k) {
+                const unsigned fl = flags[k];
+                if (!(fl & (1u << s))) continue;
+                const int o = lofs[k];
+                T ym[VEC], yp[VEC], f3[VEC], lft, rgt;
+                k_load<T, VEC>(ym, src + o - FW);
+                k_load<T, VEC>(yp, src + o + FW);
+                if (s == 3) k_load<T, VEC>(f3, FB + o);
+                xnbrs(src, o, (int)(fl >> kColShift), Lc[k], lft, rgt);
+                T res[VEC];
+                if (s < B && BC == 0 && (pr < 0 || (fl & kGhost))) {
+                    k_zero<T, VEC>(res);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        const T xm = e == 0 ? lft : Lc[k][e > 0 ? e - 1 : 0];
+                        const T xp = e == VEC - 1 ? rgt : Lc[k][e + 1 < VEC ? e + 1 : e];
+                        const T fq = s == 1 ? RF[rs3(PH)][k][e] : s == 2 ? RF[rs3(PH - 1)][k][e] : f3[e];
+                        res[e] = k_fwd<T>(Lc[k][e], xm, xp, ym[e], yp[e], Lm[k][e], Lp[k][e], fq, C0, C1, C2);
+                    }
+                }
+                const bool here = (fl & kOwned) && owned_plane;
+                if (s < B) {
+                    k_store<T, VEC>(dst + o, res);
+                    k_copy<T, VEC>(Lo[k], res);
+                    if (mid && here) k_store_nt<T, VEC>(const_cast<T *>(at(mid + (int64_t)p * sz, k)), res);
+                } else if (fl & kOwned) {
+                    k_store_nt<T, VEC>(const_cast<T *>(at(O + (int64_t)p * sz, k)), res);
+                }
+                if constexpr (RED) {
+                    if (here) {
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) {
+                            const double d = (double)res[e];
+                            es[s - 1] = fma(d, d, es[s - 1]);
+                            const double dd = d - (double)Lc[k][e];
+                            rs[s - 1] = fma(dd, dd, rs[s - 1]);
+                        }
+                    }
+                }
+            }
+            // level 0 at q-1 is dead: fetch plane q+2 into its slot
+            if (s == 1) load_u(q + 2, RU[rs3(PH + 2)]);
+        }
+        // f of plane q-1 is dead after this iteration's stages (B = 2) or
+        // waits in LDS for the last stage of the next one (B = 3); its slot
+        // takes plane q+2
+        if (B == 3) {
+#pragma unroll
+            for (int k = 0; k < KM; ++k)
+                if (flags[k] & 2u) k_store<T, VEC>(FB + lofs[k], RF[rs3(PH - 1)][k]);
+        }
+        load_f(q + 2, RF[rs3(PH + 2)]);
+        if (q + 1 <= qlast) {
+#pragma unroll
+            for (int k = 0; k < KM; ++k)
+                if (flags[k] & kValid) k_store<T, VEC>(L0p(q + 1) + lofs[k], RU[rs3(PH + 1)][k]);
+        }
+        __syncthreads();
+    };
+
+    // whole trips of three planes (one back-edge, no side exits, so each
+    // ring slot keeps its registers), then up to two planes
+    if (z0 < z1) {
+        int q = q0;
+        for (; q + 2 <= qlast; q += 3) {
+            iter(std::integral_constant<int, 0>{}, q);
+            iter(std::integral_constant<int, 1>{}, q + 1);
+            iter(std::integral_constant<int, 2>{}, q + 2);
+        }
+        if (q <= qlast) iter(std::integral_constant<int, 0>{}, q);
+        if (q + 1 <= qlast) iter(std::integral_constant<int, 1>{}, q + 1);
+    }
+
+    if constexpr (RED) {
+        double *red = reinterpret_cast<double *>(tbk_smem);
+        const int wave = tid >> 6;
+        constexpr int NW = NT / 64;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+            for (int s = 0; s < B; ++s) {
+                es[s] += __shfl_xor(es[s], off, 64);
+                rs[s] += __shfl_xor(rs[s], off, 64);
+            }
+        }
+        __syncthreads();
+        if (wlane == 0) {
+#pragma unroll
+            for (int s = 0; s < B; ++s) {
+                red[2 * B * wave + 2 * s] = es[s];
+                red[2 * B * wave + 2 * s + 1] = rs[s];
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+#pragma unroll
+            for (int s = 0; s < B; ++s) {
+                double e = 0.0, r = 0.0;
+                for (int w = 0; w < NW; ++w) {
+                    e += red[2 * B * w + 2 * s];
+                    r += red[2 * B * w + 2 * s + 1];
+                }
+                a.part[s][2 * (int64_t)Lb] = e;
+                a.part[s][2 * (int64_t)Lb + 1] = r;
+            }
+        }
+    }
+}
+
+template <typename T, int VEC, int B, int NT, int KM, int BC, bool SEG, bool RED, bool RING>
+auto tbk_fn() {
+    if constexpr (RING) return tbr_kernel<T, VEC, B, NT, KM, BC, SEG, RED>;
+    else return tbk_kernel<T, VEC, B, NT, KM, BC, SEG, RED>;
+}
+
+template <typename T, int VEC, int B, int NT, int KM, bool RING>
 hipError_t tbk_launch_t(int bc, bool reduce, const TbkTile &t, const TbkArgs &a, hipStream_t st) {
     const dim3 grid(t.nblk), block(NT);
     const size_t lds = t.lds_bytes;
 #define DCP_TBK(BCV, SEGV, REDV)                                                                     \
     do {                                                                                             \
-        auto fn = tbk_kernel<T, VEC, B, NT, KM, BCV, SEGV, REDV>;                                    \
+        auto fn = tbk_fn<T, VEC, B, NT, KM, BCV, SEGV, REDV, RING>();                                \
         hipError_t e_ = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),                      \
                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
         if (e_ != hipSuccess) return e_;                                                             \
@@ -438,17 +750,23 @@ hipError_t tbk_launch_t(int bc, bool reduce, const TbkTile &t, const TbkArgs &a,
 }
 
 // Lane shapes: 1024 lanes with two chunks each (four waves per SIMD, up to
-// 128 VGPRs) or 512 lanes with four (two waves per SIMD, up to 256 VGPRs).
+// 128 VGPRs), 512 lanes with four (two waves per SIMD, up to 256 VGPRs), or
+// the ring form with 768 lanes of two chunks (three waves per SIMD, up to 168
+// VGPRs).
 struct TbkLanes {
     int nt, km;
+    bool ring;
 };
-constexpr TbkLanes kTbkLanes[] = {{1024, 2}, {512, 4}};
+constexpr TbkLanes kTbkLanes[] = {{1024, 2, false}, {512, 4, false}, {768, 2, true}};
 
 // LDS rows of a tile: level 0 (ty + 2B rows), two planes of each level s =
-// 1 .. B-1 (ty + 2(B-s) rows each).
-int tbk_lds_rows(int B, int ty) {
-    int rows = ty + 2 * B;
+// 1 .. B-1 (ty + 2(B-s) rows each); the ring form adds a second level-0
+// plane and, with B = 3, one plane of f on the level-1 rows.
+int tbk_lds_rows(int B, int ty, bool ring) {
+    const int r0 = ty + 2 * B;
+    int rows = ring ? 2 * r0 : r0;
     for (int s = 1; s < B; ++s) rows += 2 * (ty + 2 * (B - s));
+    if (ring && B == 3) rows += r0 - 2;
     return rows;
 }
 
@@ -463,7 +781,10 @@ bool tbk_plan(int dtype, int B, int64_t nx, int64_t ny, int64_t nz, bool vec_ok,
     if (nx > (1 << 24) || nx * ny > (int64_t)INT32_MAX || nz > (1 << 29) || ny > (1 << 29)) return false;
     const int64_t ch = nx / vec;
     const int halo = (B + vec - 1) / vec;
-    const TbkLanes ln = kTbkLanes[lanes == 512 ? 1 : 0];
+    const TbkLanes ln = kTbkLanes[lanes == 512 ? 1 : lanes == 768 ? 2 : 0];
+    // the ring form addresses a chunk as a plane base plus a 32-bit offset
+    // (the tile limits below already keep its planes under 1 GiB)
+    if (ln.ring && nx * ny * esz > (int64_t)UINT32_MAX) return false;
     // Candidates: whole rows, or segments of 256, 128, 64 or 32 chunks; slabs
     // of 16, 8 or 4 rows.  Each must fit the lanes and the LDS; the planner
     // takes the one that recomputes the fewest points per owned point (the
@@ -480,7 +801,7 @@ bool tbk_plan(int dtype, int B, int64_t nx, int64_t ny, int64_t nz, bool vec_ok,
             if (force_ty > 0 && ty != force_ty) continue;
             const int r0 = ty + 2 * B;
             if ((int64_t)r0 * chf > (int64_t)ln.nt * ln.km) continue;
-            const size_t lds = (size_t)tbk_lds_rows(B, ty) * (size_t)chf * 16;
+            const size_t lds = (size_t)tbk_lds_rows(B, ty, ln.ring) * (size_t)chf * 16;
             if (lds > lds_limit) continue;
             if (lds < (size_t)(ln.nt / 64) * 2 * B * sizeof(double)) continue;
             const int64_t nslab = (ny + ty - 1) / ty;
@@ -528,22 +849,21 @@ bool tbk_plan(int dtype, int B, int64_t nx, int64_t ny, int64_t nz, bool vec_ok,
 }
 
 hipError_t launch_tbk(int dtype, int bc, bool reduce, const TbkTile &t, const TbkArgs &a, hipStream_t st) {
-    const bool n1024 = t.nt == 1024 && t.km == 2, n512 = t.nt == 512 && t.km == 4;
-    if ((!n1024 && !n512) || (t.B != 2 && t.B != 3)) return hipErrorInvalidValue;
+    const bool n1024 = t.nt == 1024 && t.km == 2, n512 = t.nt == 512 && t.km == 4, n768 = t.nt == 768 && t.km == 2;
+    if ((!n1024 && !n512 && !n768) || (t.B != 2 && t.B != 3)) return hipErrorInvalidValue;
+#define DCP_TBK_SHAPES(TT, VV, BB)                                                    \
+    do {                                                                              \
+        if (n1024) return tbk_launch_t<TT, VV, BB, 1024, 2, false>(bc, reduce, t, a, st); \
+        if (n768) return tbk_launch_t<TT, VV, BB, 768, 2, true>(bc, reduce, t, a, st);    \
+        return tbk_launch_t<TT, VV, BB, 512, 4, false>(bc, reduce, t, a, st);             \
+    } while (0)
     if (dtype == 0) {
-        if (t.B == 2) {
-            if (n1024) return tbk_launch_t<double, 2, 2, 1024, 2>(bc, reduce, t, a, st);
-            return tbk_launch_t<double, 2, 2, 512, 4>(bc, reduce, t, a, st);
-        }
-        if (n1024) return tbk_launch_t<double, 2, 3, 1024, 2>(bc, reduce, t, a, st);
-        return tbk_launch_t<double, 2, 3, 512, 4>(bc, reduce, t, a, st);
+        if (t.B == 2) DCP_TBK_SHAPES(double, 2, 2);
+        DCP_TBK_SHAPES(double, 2, 3);
     }
-    if (t.B == 2) {
-        if (n1024) return tbk_launch_t<float, 4, 2, 1024, 2>(bc, reduce, t, a, st);
-        return tbk_launch_t<float, 4, 2, 512, 4>(bc, reduce, t, a, st);
-    }
-    if (n1024) return tbk_launch_t<float, 4, 3, 1024, 2>(bc, reduce, t, a, st);
-    return tbk_launch_t<float, 4, 3, 512, 4>(bc, reduce, t, a, st);
+    if (t.B == 2) DCP_TBK_SHAPES(float, 4, 2);
+    DCP_TBK_SHAPES(float, 4, 3);
+#undef DCP_TBK_SHAPES
 }
 
 }  // namespace dcp

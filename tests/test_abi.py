@@ -336,6 +336,21 @@ def test_run_plan_reports_the_passes(L, monkeypatch):
         L.run_plan(L.F64, 8, 8, 8, 10, 2, impl=L.UNFUSED)
 
 
+def test_three_step_plan_prefers_the_ring_form(L, monkeypatch):
+    # the ring form (768 lanes) is the planner's first choice for three- and
+    # two-step passes; the 1024- and 512-lane form stays reachable through
+    # the tuning override
+    monkeypatch.delenv("DCP_TUNING", raising=False)
+    for code, shape in ((L.F64, (512, 512, 512)), (L.F32, (1024, 1024, 512)), (L.F64, (64, 64, 64)),
+                        (L.F64, (1030, 17, 9)), (L.F32, (8, 3, 2))):
+        p = L.run_plan(code, *shape, 100, 3)
+        assert p["steps_per_pass"] == 3 and p["lanes"] == 768, (shape, p)
+    monkeypatch.setenv("DCP_TUNING", "1")
+    monkeypatch.setenv("DCP_TBK_CFG", "0,0,1024")
+    p = L.run_plan(L.F64, 512, 512, 512, 100, 3)
+    assert p["steps_per_pass"] == 3 and p["lanes"] == 1024, p
+
+
 def test_tuning_overrides_need_the_master_switch(L, monkeypatch):
     # a tiling variable alone changes nothing; with DCP_TUNING=1 it is honoured
     monkeypatch.delenv("DCP_TUNING", raising=False)

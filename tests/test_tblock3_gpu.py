@@ -98,10 +98,11 @@ def test_wide_rows_keep_multi_step_passes(shape, dtype, bc, tblock):
 
 
 # every tiling the B-step kernel compiles: whole rows (a width covering the
-# row) or segments of 32 .. 256 chunks, slabs of 4 / 8 / 16 rows, 1024 or 512
-# lanes, forced through the planner's tuning override; each must give the
-# same states (a tiling that does not fit the grid leaves one-step passes)
-FORCED = [(wc, ty, lanes) for wc in (1 << 20, 32, 64, 128, 256) for ty in (4, 8, 16) for lanes in (1024, 512)]
+# row) or segments of 32 .. 256 chunks, slabs of 4 / 8 / 16 rows, the ring
+# form (768 lanes) or the plain form (1024 or 512 lanes), forced through the
+# planner's tuning override; each must give the same states (a tiling that
+# does not fit the grid leaves one-step passes)
+FORCED = [(wc, ty, lanes) for wc in (1 << 20, 32, 64, 128, 256) for ty in (4, 8, 16) for lanes in (768, 1024, 512)]
 
 
 @pytest.mark.parametrize("wc,ty,lanes", FORCED)
