@@ -48,7 +48,7 @@ KERNEL_SRCS = {1: os.path.join(ROOT, "paper_2107_00555_amd", "csrc", "dcp_kernel
                3: os.path.join(ROOT, "paper_2107_00555_amd", "csrc", "dcp_tbk.hip")}
 COUNTERS = {1: os.path.join(ROOT, "profiles", "stencil_fused_f64_512_counters.md"),
             2: os.path.join(ROOT, "profiles", "tb2_fused_f64_512_counters.md"),
-            3: os.path.join(ROOT, "profiles", "tbk3_fused_f64_512_counters.md")}
+            3: os.path.join(ROOT, "profiles", "tbr3_fused_f64_512_counters.md")}
 KERNEL_NAMES = {1: "stencil_kernel<double,2,1,4,4,PERIODIC,FWD,norms> (one step per launch)",
                 2: "tb2_kernel<double,2,4,1024,2,PERIODIC,FWD,norms> (two steps per launch)",
                 3: "tbr_kernel<double,2,3,768,2,PERIODIC,segments,norms> (three steps per launch, register rings)"}

@@ -154,8 +154,8 @@ struct RunWs {
 // LDS of one workgroup on gfx950, the most a two-step pass may plan for.
 constexpr size_t kLdsMax = 160 * 1024;
 
-// Plan of a B-step pass (dcp_tbk.hip): the ring form (768 lanes) where a
-// tile fits it, else 1024 lanes.  DCP_TBK_CFG="wc,ty,lanes" restricts the
+// Plan of a B-step pass (dcp_tbk.hip): for three steps the ring form (768
+// lanes) where a tile fits it, else 1024 lanes; for two steps the reverse.  DCP_TBK_CFG="wc,ty,lanes" restricts the
 // planner to segments of wc chunks (a value covering the row: whole rows),
 // slabs of ty rows and 768, 1024 or 512 lanes; 0 leaves a choice to the
 // planner.  DCP_TBK_SBLK sets the slabs per block of the tile order.
@@ -171,10 +171,14 @@ bool tbk_for(int dtype, const Geo &g, int B, bool vok, size_t lds_limit, TbkTile
             lanes = c == 512 || c == 768 || c == 1024 ? c : 0;
         }
     }
+    // measured at 1024x1024x512 FP64: the ring form is the faster for three
+    // steps per pass (22.4 against 24.7 ms for T = 24), the plain form for
+    // two (30.7 against 34.4 ms)
+    const int first = B == 3 ? 768 : 1024, second = B == 3 ? 1024 : 768;
     bool ok = false;
     if (lanes) ok = tbk_plan(dtype, B, g.nx, g.ny, g.nz, vok, lds_limit, lanes, wc, ty, t);
-    else ok = tbk_plan(dtype, B, g.nx, g.ny, g.nz, vok, lds_limit, 768, wc, ty, t) ||
-              tbk_plan(dtype, B, g.nx, g.ny, g.nz, vok, lds_limit, 1024, wc, ty, t);
+    else ok = tbk_plan(dtype, B, g.nx, g.ny, g.nz, vok, lds_limit, first, wc, ty, t) ||
+              tbk_plan(dtype, B, g.nx, g.ny, g.nz, vok, lds_limit, second, wc, ty, t);
     if (!ok) return false;
     if (const char *e = tuning_env("DCP_TBK_SBLK")) {
         const int h = std::atoi(e);

@@ -337,18 +337,23 @@ def test_run_plan_reports_the_passes(L, monkeypatch):
 
 
 def test_three_step_plan_prefers_the_ring_form(L, monkeypatch):
-    # the ring form (768 lanes) is the planner's first choice for three- and
-    # two-step passes; the 1024- and 512-lane form stays reachable through
-    # the tuning override
+    # the ring form (768 lanes) is the planner's first choice for three-step
+    # passes, the plain form (1024 lanes) for two-step passes over
+    # x-segments; either stays reachable through the tuning override
     monkeypatch.delenv("DCP_TUNING", raising=False)
     for code, shape in ((L.F64, (512, 512, 512)), (L.F32, (1024, 1024, 512)), (L.F64, (64, 64, 64)),
                         (L.F64, (1030, 17, 9)), (L.F32, (8, 3, 2))):
         p = L.run_plan(code, *shape, 100, 3)
         assert p["steps_per_pass"] == 3 and p["lanes"] == 768, (shape, p)
+    p = L.run_plan(L.F64, 1024, 1024, 512, 24, 2)
+    assert p["steps_per_pass"] == 2 and p["segmented"] == 1 and p["lanes"] == 1024, p
     monkeypatch.setenv("DCP_TUNING", "1")
     monkeypatch.setenv("DCP_TBK_CFG", "0,0,1024")
     p = L.run_plan(L.F64, 512, 512, 512, 100, 3)
     assert p["steps_per_pass"] == 3 and p["lanes"] == 1024, p
+    monkeypatch.setenv("DCP_TBK_CFG", "0,0,768")
+    p = L.run_plan(L.F64, 1024, 1024, 512, 24, 2)
+    assert p["steps_per_pass"] == 2 and p["lanes"] == 768, p
 
 
 def test_tuning_overrides_need_the_master_switch(L, monkeypatch):
