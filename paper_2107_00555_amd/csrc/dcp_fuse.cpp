@@ -386,19 +386,24 @@ void generate(dcp_fused *p) {
       << "}\n"
       << "#define DCP_LOWER 0x138\n"  // wave_shr:1
       << "#define DCP_UPPER 0x130\n"  // wave_shl:1
-      << "template <typename T> __device__ __forceinline__ void dcp_ldv(const T *__restrict__ a, T *o) {\n"
-      << "    typedef T vt __attribute__((ext_vector_type(V)));\n"
+      // NT: the streaming (non-temporal) hint, for data a kernel touches once
+      // (a field read only unshifted, every store), so that the rows a
+      // shifted read fetches stay in L2 for the neighbouring tiles
+      << "template <typename T, bool NT = false> __device__ __forceinline__ void dcp_ldv(const T *__restrict__ a, "
+         "T *o) {\n"
+      << "    typedef T vt __attribute__((ext_vector_type(V), aligned(sizeof(T))));\n"
       << "    vt v;\n"
-      << "    __builtin_memcpy(&v, a, sizeof(vt));\n"
+      << "    if constexpr (NT) v = __builtin_nontemporal_load(reinterpret_cast<const vt *>(a));\n"
+      << "    else __builtin_memcpy(&v, a, sizeof(vt));\n"
       << "#pragma unroll\n"
       << "    for (int j = 0; j < V; ++j) o[j] = v[j];\n"
       << "}\n"
       << "template <typename T> __device__ __forceinline__ void dcp_stv(T *__restrict__ a, const T *o) {\n"
-      << "    typedef T vt __attribute__((ext_vector_type(V)));\n"
+      << "    typedef T vt __attribute__((ext_vector_type(V), aligned(sizeof(T))));\n"
       << "    vt v;\n"
       << "#pragma unroll\n"
       << "    for (int j = 0; j < V; ++j) v[j] = o[j];\n"
-      << "    __builtin_memcpy(a, &v, sizeof(vt));\n"
+      << "    __builtin_nontemporal_store(v, reinterpret_cast<vt *>(a));\n"
       << "}\n"
       << "template <typename T, typename I> __device__ __forceinline__ void dcp_wr(T *__restrict__ a, "
          "const T *o, I i, I x, I nx) {\n"
@@ -409,9 +414,9 @@ void generate(dcp_fused *p) {
       << "}\n"
       // one queue slot: the lane's V x-points of row yy, plane zz (wrapped;
       // the start clamped into the row); returns whether it reads as data
-      << "template <typename T, typename I> __device__ __forceinline__ bool dcp_slot(const T *__restrict__ a, T *q, "
-         "I xc, I yy, I zz, I nx, I ny, I nz, int bc) {\n"
-      << "    dcp_ldv<T>(a + (xc + nx * (dcp_wrap<I>(yy, ny) + ny * dcp_wrap<I>(zz, nz))), q);\n"
+      << "template <typename T, typename I, bool NT = false> __device__ __forceinline__ bool dcp_slot(const T "
+         "*__restrict__ a, T *q, I xc, I yy, I zz, I nx, I ny, I nz, int bc) {\n"
+      << "    dcp_ldv<T, NT>(a + (xc + nx * (dcp_wrap<I>(yy, ny) + ny * dcp_wrap<I>(zz, nz))), q);\n"
       << "    return bc != 0 || (dcp_in<I>(yy, ny) && dcp_in<I>(zz, nz));\n"
       << "}\n"
       // V points (x + j + dx, yy, zz) through the boundary rule, one wrap
@@ -493,6 +498,16 @@ void generate(dcp_fused *p) {
                 loaded[o] = 1;
             }
         }
+        // a group streams (non-temporal loads) when every read of its field
+        // in this kernel is unshifted: no other tile or plane needs its lines
+        std::vector<char> streamed(grps.size(), 1);
+        for (const Rd &r : rds)
+            if (r.dx != 0 || r.dy != 0 || r.dz != 0)
+                for (size_t g = 0; g < grps.size(); ++g)
+                    if (grps[g].field == r.field) streamed[g] = 0;
+        auto slot_fn = [&](size_t g) -> std::string {
+            return std::string("dcp_slot<") + T + ", I" + (streamed[g] ? ", true" : "") + ">";
+        };
         int maxd[3] = {0, 0, 0};
         for (const Rd &r : rds) {
             maxd[0] = std::max(maxd[0], std::abs(r.dx));
@@ -555,7 +570,7 @@ void generate(dcp_fused *p) {
                 const int span = grps[g].dzhi - grps[g].dzlo + 1;
                 for (int q = 0; q < span; ++q)
                     b << "        " << T << " Q" << g << "_" << q << "[V];\n"
-                      << "        bool W" << g << "_" << q << " = dcp_slot<" << T << ", I>(m" << grps[g].field << ", Q"
+                      << "        bool W" << g << "_" << q << " = " << slot_fn(g) << "(m" << grps[g].field << ", Q"
                       << g << "_" << q << ", xc, y + (" << grps[g].dy << "), zb + (" << grps[g].dzlo + q
                       << "), nx, ny, nz, bc);\n";
                 b << "        " << T << " P" << g << "[V];\n";
@@ -608,7 +623,7 @@ void generate(dcp_fused *p) {
             // complete in order: the per-point loads above go out first, so
             // waiting for them does not wait for these)
             for (size_t g = 0; g < grps.size(); ++g)
-                b << "            const bool WP" << g << " = dcp_slot<" << T << ", I>(m" << grps[g].field << ", P" << g
+                b << "            const bool WP" << g << " = " << slot_fn(g) << "(m" << grps[g].field << ", P" << g
                   << ", xc, y + (" << grps[g].dy << "), z + (" << grps[g].dzhi + 1 << "), nx, ny, nz, bc);\n";
             // each read from its slot: element j is element j + dx of this
             // lane's vector, or of the lower / upper lane's.  In a wave with no
