@@ -256,7 +256,7 @@ def test_large_adjoint_crop_f32_vs_fp64_oracle():
     _, gw, gaw, gbw = oracle.grad_of_half_sq_dist(u0, f, tgt, C, T, bc)
     e_u, e_a, e_b = normwise(g, gw), abs(gab[0] - gaw) / abs(gaw), abs(gab[1] - gbw) / abs(gbw)
     print(f"crop f32 vs FP64 oracle: dL/du0 {e_u:.3e}, dL/dalpha {e_a:.3e}, dL/dbeta {e_b:.3e}")
-    assert e_u <= 1e-4 and e_a <= 1e-4 and e_b <= 1e-4
+    assert e_u <= 1e-5 and e_a <= 1e-5 and e_b <= 1e-5
 
 
 @pytest.mark.timeout(900)
@@ -284,4 +284,4 @@ def test_large_adjoint_full_size_f32_vs_f64():
     e_u = float((g32 - g64).abs().max() / g64.abs().max())
     e_ab = ((ab32 - ab64).abs() / ab64.abs()).cpu().numpy()
     print(f"1024x1024x512 f32 vs f64 gradient: dL/du0 {e_u:.3e}, dL/dalpha {e_ab[0]:.3e}, dL/dbeta {e_ab[1]:.3e}")
-    assert e_u <= 1e-4 and e_ab.max() <= 1e-4
+    assert e_u <= 1e-5 and e_ab.max() <= 1e-5
