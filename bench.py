@@ -15,7 +15,9 @@ N*T*K / seconds / 1e9).
 
 In the same run (--forms all, the default) every other form of the metric
 is timed on the same inputs, each in its own event-timed region: the
-unfused single-operator chain, the float32 forms, the adjoint kernel and
+unfused single-operator chain, the float32 forms, the 1024x1024x512 grid
+(rows longer than a whole-row tile), one GPU's 512x512x64 share of an
+8-way z-slab split, the adjoint kernel and
 the end-to-end gradient (forward with checkpoints + checkpointed adjoint);
 one step (and one adjoint step) run by kernels the fusing compiler
 generates (fused, and one kernel per statement) beside the hand-written
@@ -694,6 +696,31 @@ def main():
                 forms[f"wide_1024x1024x512_{dname}_tblock{tb}"] = ent
             del uw0, fw, uw, wsw, ref
             torch.cuda.empty_cache()
+
+        # one GPU's share of the 512^3 grid split into 8 z-slabs: 512 x 512 x 64
+        # planes, T = 100, FP64, periodic along z in place of the halo planes
+        # a neighbour would send (the kernels' work per GPU at its real shape;
+        # nothing crosses GPUs here)
+        sshape = (nx, ny, nz // 8)
+        us0 = u0[: nz // 8].clone()
+        fs = f64[: nz // 8].clone()
+        us = us0.clone()
+        wss = api.workspace(_lib.workspace_bytes(_lib.OP_RUN, _lib.F64, *sshape, T=T, norms=True, tblock=3), dev)
+        ref = None
+        for tb in (1, 2, 3):
+            log(f"timing one 8-way z-slab {sshape} f64 tblock={tb}")
+            us.copy_(us0)
+            api.run(us, fs, coeffs, T, bc, impl="fused", tblock=tb, norms=True, ws=wss)
+            torch.cuda.synchronize()
+            if ref is None:
+                ref = us.clone()
+            elif not torch.equal(ref, us):
+                raise RuntimeError(f"z-slab passes of {tb} steps differ from one-step passes")
+            ms_s, _, _ = timed(lambda: api.run(us, fs, coeffs, T, bc, impl="fused", tblock=tb, norms=True,
+                                               ws=wss), kk, 1, stream)
+            forms[f"zslab_512x512x64_f64_tblock{tb}"] = fused_entry(ms_s / kk, 8, tb, shape=sshape)
+        del us0, fs, us, wss, ref
+        torch.cuda.empty_cache()
 
         # adjoint kernel alone: k = 1 (no recomputation), 10 steps
         forms.update(adjoint_forms(dev, stream, u0, f64, coeffs, bc, kk))
