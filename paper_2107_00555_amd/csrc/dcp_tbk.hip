@@ -411,10 +411,11 @@ __global__ void __launch_bounds__(NT) tbk_kernel(TbkArgs a) {
     }
 }
 
-// Ring form of the same pass, for shapes with up to 168 (768 lanes) or 256
-// (512 lanes) VGPRs.  Each lane keeps, for its own chunks, the three planes
-// of every level that the next level reads (p-1, p, p+1) in registers, so
-// only the y- and x-neighbours of a point come from LDS:
+// Ring form of the same pass, compiled for 768 lanes with two chunks each
+// (three waves per SIMD, up to 168 VGPRs).  Each lane keeps, for its own
+// chunks, the three planes of every level that the next level reads (p-1,
+// p, p+1) in registers, so only the y- and x-neighbours of a point come
+// from LDS:
 //   * level 0 (u) in a ring of three planes, the load of plane q+2 issued as
 //     soon as plane q-1 is dead (after stage 1 of iteration q);
 //   * level s (1 .. B-1) in a ring of three planes, written by stage s and
