@@ -223,7 +223,11 @@ typedef struct {
     int32_t segmented;      /* multi-step passes over x-segments with a halo
                                (1) or over whole rows (0)                      */
     int32_t tile_rows;      /* rows per tile of the multi-step passes          */
-    int32_t lanes;          /* lanes per workgroup of the multi-step passes    */
+    int32_t lanes;          /* lanes per workgroup of the multi-step passes
+                               (768: the three-step passes' register-ring
+                               form, whose z-neighbours stay in registers;
+                               1024 or 512: the form that re-reads them from
+                               LDS)                                            */
 } dcp_run_info;
 
 int dcp_run_plan(int dtype, int impl, int64_t nx, int64_t ny, int64_t nz,
