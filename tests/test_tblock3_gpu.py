@@ -65,13 +65,15 @@ def test_three_step_passes_match_oracle(shape, bc):
     assert_rel("R_t", to_host(out["resid"]), r_want, 1e-12)
 
 
+@pytest.mark.parametrize("shape", [(128, 20, 18), (600, 37, 11)])
 @pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("bc", BCS)
-def test_three_step_passes_store_checkpoints_inside_a_pass(k, bc):
-    # checkpoints at the first, second or last step of a pass, norms on
-    say("tblock 3 checkpoints", k, bc)
+def test_three_step_passes_store_checkpoints_inside_a_pass(k, bc, shape):
+    # checkpoints at the first, second or last step of a pass, norms on;
+    # whole-row tiles and x-segments
+    say("tblock 3 checkpoints", k, bc, shape)
     for dtype in (torch.float64, torch.float32):
-        _same_as_single_steps((128, 20, 18), dtype, bc, 11, 3, 1200 + k, ckpt_every=k)
+        _same_as_single_steps(shape, dtype, bc, 11, 3, 1200 + k, ckpt_every=k)
 
 
 # rows longer than a whole-row tile can hold: two-step passes over x-segments
